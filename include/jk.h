@@ -1,0 +1,170 @@
+/*
+ * jk.h -- C ABI of the MI355X (gfx950) Coulomb/exchange matrix library.
+ *
+ * The library builds, for one or more symmetric density matrices D^s,
+ *
+ *     J^s_ij = sum_kl (ij|kl) D^s_kl          K^s_ik = sum_jl (ij|kl) D^s_jl
+ *
+ * (paper Section 2, eq. jk), where (ij|kl) are electron repulsion integrals
+ * over contracted Cartesian Gaussian shells (Section 2, eq. rys0), evaluated
+ * by Rys quadrature (Section 2, eqs. rys1 and rys2) on the GPU, over the
+ * shell quartets that pass the Schwarz test Q_IJ * Q_KL >= cutoff with
+ * Q_IJ = sqrt(max_{a in I, b in J} |(ab|ab)|) (Section 2, eq. schwartz).
+ * Only unique quartets are evaluated (the eight-fold permutational symmetry
+ * of Section 2).
+ *
+ * Conventions shared by every entry point:
+ *   - Basis: see jk_basis.  coefs multiply raw primitives
+ *     x^ax y^ay z^az exp(-alpha r^2) centred on the shell's atom.
+ *   - Cartesian components in reversed lexicographic order (xx, xy, xz, yy,
+ *     yz, zz for d; Section 2's index function).  Spherical shells are real
+ *     solid harmonics m = -l..l (l = 1 stays x, y, z), normalised like the
+ *     Cartesian x^l component.
+ *   - Matrices are FP64, row-major [nset][nao][nao], nao counting spherical
+ *     functions when the basis is spherical.
+ *   - Device pointers are HIP device memory on the current device.  Streams
+ *     are hipStream_t passed as void* (NULL = the null stream).
+ *   - Every function returns 0 (JK_OK) or a negative JK_E* code and never
+ *     aborts; jk_last_error() gives a thread-local message.  Errors raised
+ *     by work already enqueued on a stream surface from a later call that
+ *     synchronises (jk_build, jk_plan_create, jk_eri_block) as JK_EDEVICE.
+ */
+#ifndef JK_H
+#define JK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    JK_OK = 0,
+    JK_EINVAL = -1,        /* bad argument: sizes, ranges, non-finite values */
+    JK_EUNSUPPORTED = -2,  /* valid but not implemented (omega != 0, l > JK_LMAX) */
+    JK_ENOMEM = -3,        /* device or host allocation failed */
+    JK_EDEVICE = -4        /* a HIP call failed */
+};
+
+/* Arithmetic of the integral evaluation (Table 1's DataType). */
+enum {
+    JK_FP64 = 0,   /* every quartet in FP64 */
+    JK_MIXED = 1,  /* quartets whose bound Q_IJ Q_KL max|D_block| < mix_threshold in
+                      FP32, the rest in FP64; accumulation always FP64 */
+    JK_FP32 = 2    /* every quartet in FP32, FP64 accumulation */
+};
+
+/* jk_execute flags (Table 1's do_j / do_k). */
+enum {
+    JK_DO_J = 1,
+    JK_DO_K = 2,
+    JK_ACCUMULATE = 4  /* add into J/K instead of overwriting them */
+};
+
+#define JK_LMAX 4       /* highest shell angular momentum (g) */
+#define JK_MAXPRIM 16   /* most primitives per shell */
+
+/* Basis description, host memory, owned by the caller, read only during the
+ * call that takes it. */
+typedef struct {
+    int32_t nshell;
+    int32_t natom;
+    int32_t spherical;      /* 0 Cartesian, 1 real solid harmonics */
+    const int32_t *l;       /* [nshell] 0..JK_LMAX */
+    const int32_t *nprim;   /* [nshell] 1..JK_MAXPRIM */
+    const int32_t *atom;    /* [nshell] 0..natom-1 */
+    const double *exps;     /* [sum nprim] > 0, grouped by shell in shell order */
+    const double *coefs;    /* [sum nprim] finite, primitive normalisation folded in */
+    const double *coords;   /* [natom][3] bohr */
+} jk_basis;
+
+typedef struct jk_plan jk_plan;
+typedef struct jk_batch jk_batch;
+
+/* Statistics of a plan (host copy). */
+typedef struct {
+    int64_t nquartets;          /* significant unique shell quartets */
+    int64_t nprim_quartets;     /* primitive quartets inside them */
+    int64_t nquartets_fp32;     /* quartets run in FP32 by the last JK_MIXED execute */
+    int32_t nclasses;           /* (bra pair type, ket pair type) launches */
+    int32_t npairs;             /* shell pairs kept after screening */
+    double setup_ms;            /* jk_plan_create wall time */
+    double model_flops;         /* algorithmic FLOPs of one build with nset = 1 */
+} jk_stats;
+
+/*
+ * Build a plan for one geometry (Section 3: the molecule is the dynamic
+ * input; angular momenta and contraction patterns select the kernels).
+ * Validates the basis, copies it to the device, builds the primitive shell-
+ * pair data, the Schwarz table (on the GPU) and the screened, sorted task
+ * lists.  cutoff: Schwarz threshold (>= 0).  Synchronous; uses the null
+ * stream.  On error *out is NULL.
+ */
+int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **out);
+void jk_plan_destroy(jk_plan *plan);
+
+/* nao: size of D/J/K rows (spherical count when spherical); nao_cart: the
+ * Cartesian count the kernels work in. */
+int jk_plan_info(const jk_plan *plan, int32_t *nao, int32_t *nao_cart);
+int jk_plan_stats(const jk_plan *plan, jk_stats *stats);
+
+/* Copy the Schwarz table Q_IJ [nshell][nshell] to host memory. */
+int jk_plan_schwarz(const jk_plan *plan, double *Q_host);
+
+/*
+ * One J/K build.  D, J, K: device FP64 [nset][nao][nao]; D must be
+ * symmetric (the kernels read both triangles and assume D_kl = D_lk).
+ * J and K are overwritten unless JK_ACCUMULATE; either may be NULL when the
+ * matching JK_DO_* flag is clear.  precision: JK_FP64 / JK_MIXED / JK_FP32;
+ * mix_threshold: bound below which JK_MIXED uses FP32 (ignored otherwise).
+ * omega must be 0 (range separation -> JK_EUNSUPPORTED).  Asynchronous on
+ * stream; D/J/K must stay valid until the stream reaches this point.
+ * nset >= 1.
+ */
+int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int32_t precision,
+               double mix_threshold, double omega, double *J, double *K, void *stream);
+
+/* One-shot: plan_create + execute (J and K) + synchronise + destroy. */
+int jk_build(const jk_basis *basis, const double *D, int32_t nset, double cutoff, int32_t precision,
+             double *J, double *K, void *stream);
+
+/*
+ * Batched builds over many plans (molecules): all class work of all
+ * molecules runs from one persistent kernel over a global work queue, and
+ * the whole build is recorded once into a hipGraph and replayed.
+ * nset densities per molecule.  D[m], J[m], K[m]: device pointers for
+ * molecule m, recorded at the first jk_batch_execute; later calls must pass
+ * the same pointers (JK_EINVAL otherwise).  Plans must outlive the batch.
+ */
+int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset, int32_t precision,
+                    double mix_threshold, jk_batch **out);
+int jk_batch_execute(jk_batch *batch, const double *const *D, double *const *J, double *const *K,
+                     void *stream);
+void jk_batch_destroy(jk_batch *batch);
+
+/*
+ * Test hook: contracted Cartesian block (IJ|KL) of shells I, J, K, L
+ * (indices into the basis), computed by the same GPU kernels as the build,
+ * copied to host_out [nI][nJ][nK][nL] (Cartesian counts).  Synchronous.
+ */
+int jk_eri_block(jk_plan *plan, int32_t I, int32_t J, int32_t K, int32_t L, int32_t precision,
+                 double *host_out);
+
+/*
+ * Test hook: n-point Rys roots (t^2) and weights as the kernels evaluate
+ * them, for count values of T (host arrays); roots/weights [count][n].
+ * precision JK_FP64 or JK_FP32.  Synchronous.
+ */
+int jk_rys_eval(int32_t n, const double *T_host, int32_t count, int32_t precision, double *roots_host,
+                double *weights_host);
+
+/* Test hook: Boys F_0..F_m at count values of T as the kernels evaluate
+ * them (table + downward recursion), out [count][m+1].  m <= 1.  Synchronous. */
+int jk_boys_eval(int32_t m, const double *T_host, int32_t count, int32_t precision, double *out_host);
+
+const char *jk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JK_H */

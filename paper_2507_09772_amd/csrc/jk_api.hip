@@ -1,0 +1,816 @@
+// jk_api.hip -- host planner and C ABI of the J/K library (include/jk.h),
+// plus the small helper kernels: primitive-pair builder, Schwarz reduction,
+// spherical <-> Cartesian transforms, density block maxima, finalisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/jk.h"
+#include "jk_registry.h"
+#include "tables/jk_tables.h"
+
+namespace jk {
+ClassEntry g_classes[NCLS];
+}
+
+using namespace jk;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(e_ == hipErrorOutOfMemory ? JK_ENOMEM : JK_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);             \
+    } while (0)
+
+extern "C" const char *jk_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// device tables (one copy per device, kept until the process ends)
+// ---------------------------------------------------------------------------
+static Tables g_tab[64];
+static bool g_tab_ok[64];
+
+template <typename T>
+static int upload(T **dst, const T *src, size_t n) {
+    HIPCHK(hipMalloc(dst, sizeof(T) * n));
+    HIPCHK(hipMemcpy(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice));
+    return 0;
+}
+
+static int tables_for_device(Tables *out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(JK_EDEVICE, "device index %d out of range", dev);
+    if (!g_tab_ok[dev]) {
+        Tables t{};
+        std::vector<float> f(JKT_RYS_NCOEF);
+        for (int i = 0; i < JKT_RYS_NCOEF; ++i) f[i] = (float)jkt_rys_coef[i];
+        int rc;
+        if ((rc = upload((double **)&t.rys, jkt_rys_coef, JKT_RYS_NCOEF))) return rc;
+        if ((rc = upload((float **)&t.rys32, f.data(), f.size()))) return rc;
+        std::vector<float> hx(JKT_HERM_N), hw(JKT_HERM_N);
+        for (int i = 0; i < JKT_HERM_N; ++i) { hx[i] = (float)jkt_herm_x2[i]; hw[i] = (float)jkt_herm_w[i]; }
+        if ((rc = upload((double **)&t.hx2, jkt_herm_x2, JKT_HERM_N))) return rc;
+        if ((rc = upload((double **)&t.hw, jkt_herm_w, JKT_HERM_N))) return rc;
+        if ((rc = upload((float **)&t.hx2_32, hx.data(), hx.size()))) return rc;
+        if ((rc = upload((float **)&t.hw32, hw.data(), hw.size()))) return rc;
+        const size_t nb = sizeof(jkt_boys) / sizeof(double);
+        std::vector<float> bf(nb);
+        for (size_t i = 0; i < nb; ++i) bf[i] = (float)jkt_boys[i];
+        if ((rc = upload((double **)&t.boys, jkt_boys, nb))) return rc;
+        if ((rc = upload((float **)&t.boys32, bf.data(), nb))) return rc;
+        g_tab[dev] = t;
+        g_tab_ok[dev] = true;
+    }
+    *out = g_tab[dev];
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// helper kernels
+// ---------------------------------------------------------------------------
+struct ShellDev {
+    const int32_t *l, *nprim, *poff, *atom;
+    const double *exps, *coefs, *coords;
+};
+
+// One thread per shell pair: all primitive pairs of the pair.
+__global__ void k_pair_build(ShellDev sh, PairRec *pairs, int npair, PrimPair *pp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npair) return;
+    const PairRec pr = pairs[t];
+    const int I = pr.ish, J = pr.jsh;
+    const double *A = sh.coords + 3 * sh.atom[I];
+    const double *B = sh.coords + 3 * sh.atom[J];
+    const double ab2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+    const int nj = sh.nprim[J];
+    for (int ip = 0; ip < sh.nprim[I]; ++ip)
+        for (int jp = 0; jp < nj; ++jp) {
+            const double a = sh.exps[sh.poff[I] + ip], b = sh.exps[sh.poff[J] + jp];
+            const double p = a + b;
+            PrimPair r;
+            r.p = p;
+            r.h = 0.5 / p;
+            r.kp = sh.coefs[sh.poff[I] + ip] * sh.coefs[sh.poff[J] + jp] * exp(-a * b / p * ab2) / p;
+            r.pad = 0.0;
+            for (int x = 0; x < 3; ++x) {
+                r.P[x] = (a * A[x] + b * B[x]) / p;
+                r.PA[x] = r.P[x] - A[x];
+            }
+            pp[pr.pp_off + ip * nj + jp] = r;
+        }
+}
+
+// q of each pair from its exported diagonal block (IJ|IJ): sqrt(max_ab |(ab|ab)|)
+__global__ void k_schwarz(const double *blocks, int nab, const int32_t *pair_ids, int n, PairRec *pairs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double *b = blocks + (int64_t)t * nab * nab;
+    double m = 0.0;
+    for (int e = 0; e < nab; ++e) m = fmax(m, fabs(b[e * nab + e]));
+    pairs[pair_ids[t]].q = sqrt(m);
+}
+
+__global__ void k_fill(double *p, int64_t n, double v) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) p[t] = v;
+}
+
+struct AoMaps {
+    const int32_t *sh_c, *comp_c;  // Cartesian AO -> shell, component
+    const int32_t *sh_e, *comp_e;  // external AO -> shell, component
+    const int32_t *l, *aoc, *aoe;  // per shell
+    const double *c2s;             // concatenated T_l, rows m, cols Cartesian
+};
+
+__device__ __forceinline__ const double *c2s_of(const AoMaps &m, int l) { return m.c2s + jkt_c2s_offset[0] * 0 + (l == 0 ? jkt_c2s_offset[0] : l == 1 ? jkt_c2s_offset[1] : l == 2 ? jkt_c2s_offset[2] : l == 3 ? jkt_c2s_offset[3] : jkt_c2s_offset[4]); }
+
+// Dc[s][a][b] = sum_{m, n} T_I[m][a] D[s][m][n] T_J[n][b]  (D spherical)
+__global__ void k_sph_to_cart(AoMaps m, const double *D, double *Dc, int nao, int naoc, int nset) {
+    const int64_t tot = (int64_t)nset * naoc * naoc;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(t / ((int64_t)naoc * naoc));
+        const int a = (int)((t / naoc) % naoc), b = (int)(t % naoc);
+        const int I = m.sh_c[a], J = m.sh_c[b];
+        const int li = m.l[I], lj = m.l[J];
+        const int ca = m.comp_c[a], cb = m.comp_c[b];
+        const double *Ti = c2s_of(m, li), *Tj = c2s_of(m, lj);
+        const int nci = ncart(li), ncj = ncart(lj);
+        const double *Ds = D + (int64_t)s * nao * nao;
+        double acc = 0.0;
+        for (int i = 0; i < 2 * li + 1; ++i) {
+            const double ti = Ti[i * nci + ca];
+            if (ti == 0.0) continue;
+            double r = 0.0;
+            for (int j = 0; j < 2 * lj + 1; ++j) r += Ds[(int64_t)(m.aoe[I] + i) * nao + m.aoe[J] + j] * Tj[j * ncj + cb];
+            acc += ti * r;
+        }
+        Dc[t] = acc;
+    }
+}
+
+// out[s] (+)= T (X + X^T) T^T, or X + X^T for Cartesian bases
+__global__ void k_finalize(AoMaps m, const double *X, double *out, int nao, int naoc, int nset, int spherical, int accumulate) {
+    const int64_t tot = (int64_t)nset * nao * nao;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int s = (int)(t / ((int64_t)nao * nao));
+        const int i = (int)((t / nao) % nao), j = (int)(t % nao);
+        const double *Xs = X + (int64_t)s * naoc * naoc;
+        double v;
+        if (!spherical) {
+            v = Xs[(int64_t)i * naoc + j] + Xs[(int64_t)j * naoc + i];
+        } else {
+            const int I = m.sh_e[i], J = m.sh_e[j];
+            const int li = m.l[I], lj = m.l[J];
+            const int mi = m.comp_e[i], mj = m.comp_e[j];
+            const int nci = ncart(li), ncj = ncart(lj);
+            const double *Ti = c2s_of(m, li) + mi * nci, *Tj = c2s_of(m, lj) + mj * ncj;
+            v = 0.0;
+            for (int a = 0; a < nci; ++a) {
+                if (Ti[a] == 0.0) continue;
+                const int ga = m.aoc[I] + a;
+                double r = 0.0;
+                for (int b = 0; b < ncj; ++b) {
+                    const int gb = m.aoc[J] + b;
+                    r += (Xs[(int64_t)ga * naoc + gb] + Xs[(int64_t)gb * naoc + ga]) * Tj[b];
+                }
+                v += Ti[a] * r;
+            }
+        }
+        out[t] = accumulate ? out[t] + v : v;
+    }
+}
+
+// dmax[I][J] = max_s max_{a in I, b in J} |Dc[s][a][b]|
+__global__ void k_dmax(const double *Dc, const int32_t *aoc, const int32_t *l, int ns, int naoc, int nset, float *dmax) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ns * ns) return;
+    const int I = t / ns, J = t % ns;
+    double m = 0.0;
+    for (int s = 0; s < nset; ++s)
+        for (int a = 0; a < ncart(l[I]); ++a)
+            for (int b = 0; b < ncart(l[J]); ++b)
+                m = fmax(m, fabs(Dc[(int64_t)s * naoc * naoc + (int64_t)(aoc[I] + a) * naoc + aoc[J] + b]));
+    dmax[t] = (float)m;
+}
+
+template <int N, typename R>
+__global__ void k_rys_eval(Tables tab, const double *T, int n, double *u, double *w) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    R uu[N], ww[N];
+    rys_roots<N, R>(T[t], tab, uu, ww);
+    for (int i = 0; i < N; ++i) {
+        u[t * N + i] = (double)uu[i];
+        w[t * N + i] = (double)ww[i];
+    }
+}
+
+template <typename R>
+__global__ void k_boys_eval(Tables tab, const double *T, int n, double *out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    R u, w;
+    rys1<R>(T[t], TabSel<R>::boys(tab), u, w);
+    out[2 * t] = (double)w;            // F_0
+    out[2 * t + 1] = (double)(u * w);  // F_1
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    template <typename T> T *as() const { return (T *)p; }
+};
+
+struct ClassTask {
+    int li, lj, lk, ll;
+    int bt, kt, same, npb, npk, nbra, ntiles;
+    int64_t nq, npq;
+    double flops;
+    int32_t *d_bra = nullptr, *d_cnt = nullptr, *d_tile = nullptr;
+    const int32_t *d_ket = nullptr;
+};
+
+struct jk_plan {
+    int ns = 0, natom = 0, sph = 0, nao = 0, naoc = 0;
+    double cutoff = 0.0;
+    std::vector<int32_t> l, nprim, atom, poff, aoc, aoe;
+    std::vector<int32_t> pair_of;  // [ns*ns] -> pair index
+    std::vector<PairRec> hpairs;
+    std::vector<double> Qsh;
+    std::vector<ClassTask> cls;
+    std::vector<void *> allocs;  // everything below is freed with the plan
+    ShellDev sh{};
+    PairRec *d_pairs = nullptr;
+    PrimPair *d_pp = nullptr;
+    AoMaps maps{};
+    double *d_Jc = nullptr, *d_Kc = nullptr, *d_Dc = nullptr;
+    int scratch_nset = 0, dc_nset = 0;
+    float *d_dmax = nullptr;
+    Tables tab{};
+    jk_stats stats{};
+    int device = 0;
+
+    template <typename T>
+    int alloc(T **p, size_t n) {
+        if (n == 0) n = 1;
+        hipError_t e = hipMalloc((void **)p, sizeof(T) * n);
+        if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? JK_ENOMEM : JK_EDEVICE, "hipMalloc(%zu): %s", sizeof(T) * n, hipGetErrorString(e));
+        allocs.push_back(*p);
+        return 0;
+    }
+    template <typename T>
+    int put(T **p, const std::vector<T> &v) {
+        int rc = alloc(p, v.size());
+        if (rc) return rc;
+        if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+        return 0;
+    }
+    ~jk_plan() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+static int validate_basis(const jk_basis *b) {
+    if (!b) return fail(JK_EINVAL, "basis is NULL");
+    if (b->nshell < 1 || b->natom < 1) return fail(JK_EINVAL, "nshell and natom must be >= 1");
+    if (!b->l || !b->nprim || !b->atom || !b->exps || !b->coefs || !b->coords) return fail(JK_EINVAL, "NULL basis array");
+    if (b->spherical != 0 && b->spherical != 1) return fail(JK_EINVAL, "spherical must be 0 or 1");
+    int64_t np = 0;
+    for (int i = 0; i < b->nshell; ++i) {
+        if (b->l[i] < 0 || b->l[i] > JK_LMAX) return fail(JK_EINVAL, "shell %d: l=%d outside 0..%d", i, b->l[i], JK_LMAX);
+        if (b->l[i] > LMAX_BUILT) return fail(JK_EUNSUPPORTED, "shell %d: l=%d above the built maximum %d", i, b->l[i], LMAX_BUILT);
+        if (b->nprim[i] < 1 || b->nprim[i] > JK_MAXPRIM) return fail(JK_EINVAL, "shell %d: nprim=%d outside 1..%d", i, b->nprim[i], JK_MAXPRIM);
+        if (b->atom[i] < 0 || b->atom[i] >= b->natom) return fail(JK_EINVAL, "shell %d: atom %d out of range", i, b->atom[i]);
+        np += b->nprim[i];
+    }
+    for (int64_t k = 0; k < np; ++k) {
+        if (!(std::isfinite(b->exps[k]) && b->exps[k] > 0.0)) return fail(JK_EINVAL, "primitive %lld: exponent must be finite and > 0", (long long)k);
+        if (!std::isfinite(b->coefs[k])) return fail(JK_EINVAL, "primitive %lld: coefficient not finite", (long long)k);
+    }
+    for (int k = 0; k < 3 * b->natom; ++k)
+        if (!std::isfinite(b->coords[k])) return fail(JK_EINVAL, "coordinate %d not finite", k);
+    return 0;
+}
+
+// per primitive quartet algorithmic FLOPs (roots, recurrences, assembly) and
+// per contracted quartet digestion FLOPs (J and K, one density)
+static double flops_prim(int li, int lj, int lk, int ll) {
+    const int nr = nroots(li, lj, lk, ll);
+    const double nc = (double)ncart(li) * ncart(lj) * ncart(lk) * ncart(ll);
+    const double rec = 5.0 * (li + lj + 1) * (lk + ll + 1) + 2.0 * (li + 1) * (lj + 1) * (lk + ll + 1) +
+                       2.0 * (li + 1) * (lj + 1) * (lk + 1) * (ll + 1);
+    const double roots = nr == 1 ? 40.0 : 56.0 * nr;
+    return 3.0 * nr * nc + 3.0 * nr * rec + roots + 30.0;
+}
+static double flops_digest(int li, int lj, int lk, int ll) {
+    return 12.0 * ncart(li) * ncart(lj) * ncart(lk) * ncart(ll);
+}
+
+static int launch_export(jk_plan *P, int li, int lj, int lk, int ll, int precision, const int32_t *d_qb, const int32_t *d_qk,
+                         int nq, double *d_out, hipStream_t s) {
+    const ClassEntry &e = g_classes[class_id(li, lj, lk, ll)];
+    Launcher f = precision == JK_FP64 ? e.ex64 : e.ex32;
+    if (!f) return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) not built", li, lj, lk, ll);
+    JkArgs a{};
+    a.pairs = P->d_pairs;
+    a.pp = P->d_pp;
+    a.q_bra = d_qb;
+    a.q_ket = d_qk;
+    a.nq = nq;
+    a.out = d_out;
+    a.tab = P->tab;
+    HIPCHK(f(a, s));
+    return 0;
+}
+
+extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **out) {
+    if (!out) return fail(JK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_basis(basis);
+    if (rc) return rc;
+    if (!(std::isfinite(cutoff) && cutoff >= 0.0)) return fail(JK_EINVAL, "cutoff must be finite and >= 0");
+    const auto t0 = std::chrono::steady_clock::now();
+    jk_plan *P = new (std::nothrow) jk_plan();
+    if (!P) return fail(JK_ENOMEM, "host allocation failed");
+    std::unique_ptr<jk_plan> guard(P);
+    HIPCHK(hipGetDevice(&P->device));
+    if ((rc = tables_for_device(&P->tab))) return rc;
+    const int ns = P->ns = basis->nshell;
+    P->natom = basis->natom;
+    P->sph = basis->spherical;
+    P->cutoff = cutoff;
+    P->l.assign(basis->l, basis->l + ns);
+    P->nprim.assign(basis->nprim, basis->nprim + ns);
+    P->atom.assign(basis->atom, basis->atom + ns);
+    P->poff.resize(ns + 1);
+    P->aoc.resize(ns + 1);
+    P->aoe.resize(ns + 1);
+    P->poff[0] = P->aoc[0] = P->aoe[0] = 0;
+    for (int i = 0; i < ns; ++i) {
+        P->poff[i + 1] = P->poff[i] + P->nprim[i];
+        P->aoc[i + 1] = P->aoc[i] + ncart(P->l[i]);
+        P->aoe[i + 1] = P->aoe[i] + (P->sph ? 2 * P->l[i] + 1 : ncart(P->l[i]));
+    }
+    P->naoc = P->aoc[ns];
+    P->nao = P->aoe[ns];
+    const int nprim_tot = P->poff[ns];
+
+    // shell types (l, nprim), ordered by l then nprim, both descending
+    std::vector<std::pair<int, int>> keys;
+    for (int i = 0; i < ns; ++i) keys.push_back({P->l[i], P->nprim[i]});
+    std::sort(keys.begin(), keys.end(), [](auto &x, auto &y) { return x > y; });
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    const int ntype = (int)keys.size();
+    std::vector<int> stype(ns);
+    for (int i = 0; i < ns; ++i)
+        stype[i] = (int)(std::find(keys.begin(), keys.end(), std::make_pair(P->l[i], P->nprim[i])) - keys.begin());
+
+    // oriented pairs, grouped by pair type (t1 <= t2)
+    std::vector<std::vector<PairRec>> by_type(ntype * ntype);
+    for (int I = 0; I < ns; ++I)
+        for (int J = 0; J <= I; ++J) {
+            int a = I, b = J;
+            if (stype[a] > stype[b]) std::swap(a, b);
+            PairRec r{};
+            r.ish = a;
+            r.jsh = b;
+            r.aoi = P->aoc[a];
+            r.aoj = P->aoc[b];
+            r.npp = P->nprim[a] * P->nprim[b];
+            const double *A = basis->coords + 3 * P->atom[a], *B = basis->coords + 3 * P->atom[b];
+            for (int x = 0; x < 3; ++x) r.ab[x] = A[x] - B[x];
+            by_type[stype[a] * ntype + stype[b]].push_back(r);
+        }
+    std::vector<int> ptype_first, ptype_count, ptype_key;  // pair types present
+    int npp_tot = 0;
+    for (int t = 0; t < ntype * ntype; ++t) {
+        if (by_type[t].empty()) continue;
+        ptype_first.push_back((int)P->hpairs.size());
+        ptype_count.push_back((int)by_type[t].size());
+        ptype_key.push_back(t);
+        for (auto &r : by_type[t]) {
+            r.pp_off = npp_tot;
+            npp_tot += r.npp;
+            P->hpairs.push_back(r);
+        }
+    }
+    const int npair = (int)P->hpairs.size();
+    P->pair_of.assign((size_t)ns * ns, -1);
+    for (int p = 0; p < npair; ++p) {
+        P->pair_of[(size_t)P->hpairs[p].ish * ns + P->hpairs[p].jsh] = p;
+        P->pair_of[(size_t)P->hpairs[p].jsh * ns + P->hpairs[p].ish] = p;
+    }
+
+    // device copies of the basis and the pair data
+    int32_t *d_l, *d_np, *d_poff, *d_atom, *d_aoc, *d_aoe;
+    double *d_exps, *d_coefs, *d_coords;
+    if ((rc = P->put(&d_l, P->l)) || (rc = P->put(&d_np, P->nprim)) || (rc = P->put(&d_poff, P->poff)) ||
+        (rc = P->put(&d_atom, P->atom)) || (rc = P->put(&d_aoc, P->aoc)) || (rc = P->put(&d_aoe, P->aoe)))
+        return rc;
+    if ((rc = P->put(&d_exps, std::vector<double>(basis->exps, basis->exps + nprim_tot))) ||
+        (rc = P->put(&d_coefs, std::vector<double>(basis->coefs, basis->coefs + nprim_tot))) ||
+        (rc = P->put(&d_coords, std::vector<double>(basis->coords, basis->coords + 3 * P->natom))))
+        return rc;
+    P->sh = ShellDev{d_l, d_np, d_poff, d_atom, d_exps, d_coefs, d_coords};
+    if ((rc = P->put(&P->d_pairs, P->hpairs))) return rc;
+    if ((rc = P->alloc(&P->d_pp, npp_tot))) return rc;
+    hipLaunchKernelGGL(k_pair_build, dim3((npair + 127) / 128), dim3(128), 0, 0, P->sh, P->d_pairs, npair, P->d_pp);
+    HIPCHK(hipGetLastError());
+
+    // Schwarz factors: exported diagonal blocks (IJ|IJ) per pair type
+    for (size_t pt = 0; pt < ptype_first.size(); ++pt) {
+        const int first = ptype_first[pt], cnt = ptype_count[pt];
+        const PairRec &r0 = P->hpairs[first];
+        const int li = P->l[r0.ish], lj = P->l[r0.jsh];
+        const int nab = ncart(li) * ncart(lj);
+        std::vector<int32_t> ids(cnt);
+        std::iota(ids.begin(), ids.end(), first);
+        int32_t *d_ids;
+        double *d_blk;
+        if ((rc = P->put(&d_ids, ids))) return rc;
+        if ((rc = P->alloc(&d_blk, (size_t)cnt * nab * nab))) return rc;
+        if ((rc = launch_export(P, li, lj, li, lj, JK_FP64, d_ids, d_ids, cnt, d_blk, 0))) return rc;
+        hipLaunchKernelGGL(k_schwarz, dim3((cnt + 127) / 128), dim3(128), 0, 0, d_blk, nab, d_ids, cnt, P->d_pairs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipFree(d_blk));
+        P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)d_blk));
+    }
+    HIPCHK(hipMemcpy(P->hpairs.data(), P->d_pairs, sizeof(PairRec) * npair, hipMemcpyDeviceToHost));
+    P->Qsh.assign((size_t)ns * ns, 0.0);
+    double qmax = 0.0;
+    for (auto &r : P->hpairs) {
+        P->Qsh[(size_t)r.ish * ns + r.jsh] = P->Qsh[(size_t)r.jsh * ns + r.ish] = r.q;
+        qmax = std::max(qmax, r.q);
+    }
+
+    // per pair type: pairs that can pass the test with some partner, by q descending
+    const int npt = (int)ptype_first.size();
+    std::vector<std::vector<int32_t>> sorted(npt);
+    std::vector<std::vector<double>> sortedq(npt);
+    std::vector<int32_t *> d_sorted(npt, nullptr);
+    for (int pt = 0; pt < npt; ++pt) {
+        auto &v = sorted[pt];
+        for (int k = 0; k < ptype_count[pt]; ++k) {
+            const int p = ptype_first[pt] + k;
+            if (P->hpairs[p].q * qmax >= cutoff && P->hpairs[p].q > 0.0) v.push_back(p);
+        }
+        std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return P->hpairs[x].q > P->hpairs[y].q; });
+        for (int p : v) sortedq[pt].push_back(P->hpairs[p].q);
+        if (!v.empty() && (rc = P->put(&d_sorted[pt], v))) return rc;
+    }
+    // classes: unordered pairs of pair types, bra = larger (l1, l2), ties by type index
+    auto lkey = [&](int pt) { const PairRec &r = P->hpairs[ptype_first[pt]]; return std::make_pair(P->l[r.ish], P->l[r.jsh]); };
+    int64_t nq_tot = 0, npq_tot = 0;
+    double flops_tot = 0.0;
+    for (int x = 0; x < npt; ++x)
+        for (int y = 0; y <= x; ++y) {
+            int bt = x, kt = y;
+            if (lkey(kt) > lkey(bt)) std::swap(bt, kt);
+            if (sorted[bt].empty() || sorted[kt].empty()) continue;
+            ClassTask c{};
+            c.li = lkey(bt).first; c.lj = lkey(bt).second; c.lk = lkey(kt).first; c.ll = lkey(kt).second;
+            c.bt = bt; c.kt = kt; c.same = bt == kt;
+            c.npb = P->hpairs[ptype_first[bt]].npp;
+            c.npk = P->hpairs[ptype_first[kt]].npp;
+            const int qpt = quartets_per_tile(c.li, c.lj, c.lk, c.ll);
+            std::vector<int32_t> bl, cn, to;
+            const auto &kq = sortedq[kt];
+            int64_t tiles = 0;
+            for (size_t i = 0; i < sorted[bt].size(); ++i) {
+                const double qb = sortedq[bt][i];
+                // kets j with qb * kq[j] >= cutoff form a prefix
+                size_t lo = 0, hi = kq.size();
+                while (lo < hi) {
+                    const size_t mid = (lo + hi) / 2;
+                    if (qb * kq[mid] >= cutoff) lo = mid + 1;
+                    else hi = mid;
+                }
+                size_t cnt = lo;
+                if (c.same) cnt = std::min(cnt, i + 1);
+                if (cnt == 0) continue;
+                bl.push_back(sorted[bt][i]);
+                cn.push_back((int32_t)cnt);
+                to.push_back((int32_t)tiles);
+                tiles += (cnt + qpt - 1) / qpt;
+                c.nq += cnt;
+            }
+            if (c.nq == 0) continue;
+            if (tiles > INT32_MAX) return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has too many tiles", c.li, c.lj, c.lk, c.ll);
+            c.nbra = (int)bl.size();
+            c.ntiles = (int)tiles;
+            c.npq = c.nq * c.npb * c.npk;
+            c.flops = (double)c.npq * flops_prim(c.li, c.lj, c.lk, c.ll) + (double)c.nq * flops_digest(c.li, c.lj, c.lk, c.ll);
+            if ((rc = P->put(&c.d_bra, bl)) || (rc = P->put(&c.d_cnt, cn)) || (rc = P->put(&c.d_tile, to))) return rc;
+            c.d_ket = d_sorted[kt];
+            if (!g_classes[class_id(c.li, c.lj, c.lk, c.ll)].jk64)
+                return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) not built", c.li, c.lj, c.lk, c.ll);
+            nq_tot += c.nq;
+            npq_tot += c.npq;
+            flops_tot += c.flops;
+            P->cls.push_back(c);
+        }
+    // heaviest classes first
+    std::stable_sort(P->cls.begin(), P->cls.end(), [](const ClassTask &a, const ClassTask &b) { return a.flops > b.flops; });
+
+    // AO maps for the spherical transforms
+    std::vector<int32_t> shc(P->naoc), cc(P->naoc), she(P->nao), ce(P->nao);
+    for (int i = 0; i < ns; ++i) {
+        for (int k = 0; k < P->aoc[i + 1] - P->aoc[i]; ++k) { shc[P->aoc[i] + k] = i; cc[P->aoc[i] + k] = k; }
+        for (int k = 0; k < P->aoe[i + 1] - P->aoe[i]; ++k) { she[P->aoe[i] + k] = i; ce[P->aoe[i] + k] = k; }
+    }
+    int32_t *d_shc, *d_cc, *d_she, *d_ce;
+    double *d_c2s;
+    if ((rc = P->put(&d_shc, shc)) || (rc = P->put(&d_cc, cc)) || (rc = P->put(&d_she, she)) || (rc = P->put(&d_ce, ce)) ||
+        (rc = P->put(&d_c2s, std::vector<double>(jkt_c2s, jkt_c2s + JKT_C2S_N))))
+        return rc;
+    P->maps = AoMaps{d_shc, d_cc, d_she, d_ce, d_l, d_aoc, d_aoe, d_c2s};
+    HIPCHK(hipDeviceSynchronize());
+
+    P->stats.nquartets = nq_tot;
+    P->stats.nprim_quartets = npq_tot;
+    P->stats.nclasses = (int32_t)P->cls.size();
+    P->stats.npairs = 0;
+    for (auto &v : sorted) P->stats.npairs += (int32_t)v.size();
+    P->stats.model_flops = flops_tot;
+    P->stats.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = guard.release();
+    return JK_OK;
+}
+
+extern "C" void jk_plan_destroy(jk_plan *plan) { delete plan; }
+
+extern "C" int jk_plan_info(const jk_plan *P, int32_t *nao, int32_t *nao_cart) {
+    if (!P) return fail(JK_EINVAL, "plan is NULL");
+    if (nao) *nao = P->nao;
+    if (nao_cart) *nao_cart = P->naoc;
+    return 0;
+}
+
+extern "C" int jk_plan_stats(const jk_plan *P, jk_stats *st) {
+    if (!P || !st) return fail(JK_EINVAL, "NULL argument");
+    *st = P->stats;
+    return 0;
+}
+
+extern "C" int jk_plan_schwarz(const jk_plan *P, double *Q) {
+    if (!P || !Q) return fail(JK_EINVAL, "NULL argument");
+    std::memcpy(Q, P->Qsh.data(), sizeof(double) * P->Qsh.size());
+    return 0;
+}
+
+static int grid_for(int64_t n, int block) { return (int)std::min<int64_t>((n + block - 1) / block, 65536); }
+
+static int ensure_scratch(jk_plan *P, int nset, bool need_dc) {
+    const size_t m = (size_t)P->naoc * P->naoc;
+    if (P->scratch_nset < nset) {
+        if (P->d_Jc) { (void)hipFree(P->d_Jc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Jc)); }
+        if (P->d_Kc) { (void)hipFree(P->d_Kc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Kc)); }
+        P->d_Jc = P->d_Kc = nullptr;
+        P->scratch_nset = 0;
+        int rc;
+        if ((rc = P->alloc(&P->d_Jc, m * nset)) || (rc = P->alloc(&P->d_Kc, m * nset))) return rc;
+        P->scratch_nset = nset;
+    }
+    if (need_dc && P->dc_nset < nset) {
+        if (P->d_Dc) { (void)hipFree(P->d_Dc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Dc)); }
+        P->d_Dc = nullptr;
+        P->dc_nset = 0;
+        int rc;
+        if ((rc = P->alloc(&P->d_Dc, m * nset))) return rc;
+        P->dc_nset = nset;
+    }
+    if (!P->d_dmax) {
+        int rc;
+        if ((rc = P->alloc(&P->d_dmax, (size_t)P->ns * P->ns))) return rc;
+    }
+    return 0;
+}
+
+extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision, double mix_threshold,
+                          double omega, double *J, double *K, void *stream) {
+    if (!P) return fail(JK_EINVAL, "plan is NULL");
+    if (!D || nset < 1) return fail(JK_EINVAL, "D must be non-NULL and nset >= 1");
+    const bool do_j = flags & JK_DO_J, do_k = flags & JK_DO_K;
+    if (flags & ~(JK_DO_J | JK_DO_K | JK_ACCUMULATE)) return fail(JK_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((do_j && !J) || (do_k && !K)) return fail(JK_EINVAL, "J/K output missing for a requested matrix");
+    if (precision != JK_FP64 && precision != JK_MIXED && precision != JK_FP32) return fail(JK_EINVAL, "bad precision %d", precision);
+    if (precision == JK_MIXED && !(std::isfinite(mix_threshold) && mix_threshold >= 0.0)) return fail(JK_EINVAL, "mix_threshold must be finite and >= 0");
+    if (omega != 0.0) return fail(JK_EUNSUPPORTED, "range-separated Coulomb (omega != 0) is not implemented");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != P->device) return fail(JK_EINVAL, "plan was created on device %d, current device is %d", P->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = ensure_scratch(P, nset, P->sph))) return rc;
+    const size_t m = (size_t)P->naoc * P->naoc;
+    const double *Dc = D;
+    if (P->sph) {
+        hipLaunchKernelGGL(k_sph_to_cart, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->maps, D, P->d_Dc, P->nao, P->naoc, nset);
+        HIPCHK(hipGetLastError());
+        Dc = P->d_Dc;
+    }
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Jc, (int64_t)(nset * m), 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Kc, (int64_t)(nset * m), 0.0);
+    HIPCHK(hipGetLastError());
+    if (precision == JK_MIXED) {
+        hipLaunchKernelGGL(k_dmax, dim3((P->ns * P->ns + 255) / 256), dim3(256), 0, s, Dc, P->maps.aoc, P->maps.l, P->ns, P->naoc, nset, P->d_dmax);
+        HIPCHK(hipGetLastError());
+    }
+    JkArgs a{};
+    a.pairs = P->d_pairs;
+    a.pp = P->d_pp;
+    a.D = Dc;
+    a.J = P->d_Jc;
+    a.K = P->d_Kc;
+    a.mstride = (int64_t)m;
+    a.nao = P->naoc;
+    a.nset = nset;
+    a.do_j = do_j;
+    a.do_k = do_k;
+    a.dmax = P->d_dmax;
+    a.nshell = P->ns;
+    a.mix_thr = mix_threshold;
+    a.tab = P->tab;
+    for (const ClassTask &c : P->cls) {
+        const ClassEntry &e = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
+        a.bra_list = c.d_bra;
+        a.ket_list = c.d_ket;
+        a.bra_cnt = c.d_cnt;
+        a.tile_off = c.d_tile;
+        a.nbra = c.nbra;
+        a.ntiles = c.ntiles;
+        a.same = c.same;
+        a.npb = c.npb;
+        a.npk = c.npk;
+        if (precision == JK_FP64 || precision == JK_MIXED) {
+            a.sel = precision == JK_MIXED ? SEL_HIGH : SEL_ALL;
+            HIPCHK(e.jk64(a, s));
+        }
+        if (precision == JK_FP32 || precision == JK_MIXED) {
+            a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
+            HIPCHK(e.jk32(a, s));
+        }
+    }
+    const int acc = (flags & JK_ACCUMULATE) ? 1 : 0;
+    const int64_t mo = (int64_t)nset * P->nao * P->nao;
+    if (do_j) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Jc, J, P->nao, P->naoc, nset, P->sph, acc);
+    if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Kc, K, P->nao, P->naoc, nset, P->sph, acc);
+    HIPCHK(hipGetLastError());
+    return JK_OK;
+}
+
+extern "C" int jk_build(const jk_basis *basis, const double *D, int32_t nset, double cutoff, int32_t precision, double *J, double *K,
+                        void *stream) {
+    jk_plan *P = nullptr;
+    int rc = jk_plan_create(basis, cutoff, &P);
+    if (rc) return rc;
+    rc = jk_execute(P, D, nset, JK_DO_J | JK_DO_K, precision, 1e-4, 0.0, J, K, stream);
+    if (rc == 0) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    }
+    jk_plan_destroy(P);
+    return rc;
+}
+
+extern "C" int jk_eri_block(jk_plan *P, int32_t I, int32_t J, int32_t K, int32_t L, int32_t precision, double *host_out) {
+    if (!P || !host_out) return fail(JK_EINVAL, "NULL argument");
+    const int ns = P->ns;
+    if (I < 0 || J < 0 || K < 0 || L < 0 || I >= ns || J >= ns || K >= ns || L >= ns) return fail(JK_EINVAL, "shell index out of range");
+    if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
+    int pb = P->pair_of[(size_t)I * ns + J], pk = P->pair_of[(size_t)K * ns + L];
+    const PairRec &rb0 = P->hpairs[pb], &rk0 = P->hpairs[pk];
+    auto lk = [&](const PairRec &r) { return std::make_pair(P->l[r.ish], P->l[r.jsh]); };
+    bool swap = lk(rk0) > lk(rb0);
+    if (swap) std::swap(pb, pk);
+    const PairRec &rb = P->hpairs[pb], &rk = P->hpairs[pk];
+    const int li = P->l[rb.ish], lj = P->l[rb.jsh], lk2 = P->l[rk.ish], ll = P->l[rk.jsh];
+    const int ni = ncart(li), nj = ncart(lj), nk = ncart(lk2), nl = ncart(ll);
+    int32_t *d_q;
+    double *d_out;
+    HIPCHK(hipMalloc(&d_q, 2 * sizeof(int32_t)));
+    const int32_t qs[2] = {pb, pk};
+    HIPCHK(hipMemcpy(d_q, qs, sizeof qs, hipMemcpyHostToDevice));
+    HIPCHK(hipMalloc(&d_out, sizeof(double) * ni * nj * nk * nl));
+    int rc = launch_export(P, li, lj, lk2, ll, precision, d_q, d_q + 1, 1, d_out, 0);
+    std::vector<double> blk((size_t)ni * nj * nk * nl);
+    if (!rc) {
+        hipError_t e = hipMemcpy(blk.data(), d_out, sizeof(double) * blk.size(), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail(JK_EDEVICE, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(d_q);
+    (void)hipFree(d_out);
+    if (rc) return rc;
+    // blk is [a in rb.ish][b in rb.jsh][c in rk.ish][d in rk.jsh]; map to (I J | K L)
+    const int sh[4] = {rb.ish, rb.jsh, rk.ish, rk.jsh};
+    const int dims[4] = {ni, nj, nk, nl};
+    const int want[4] = {I, J, K, L};
+    // position of each requested index among the block axes
+    int pos[4];
+    {
+        const int wb[2] = {swap ? K : I, swap ? L : J};
+        const int wk[2] = {swap ? I : K, swap ? J : L};
+        // bra block axes 0,1 hold (rb.ish, rb.jsh) == {wb[0], wb[1]} in some order
+        int bpos0 = (rb.ish == wb[0]) ? 0 : 1;
+        if (wb[0] == wb[1]) bpos0 = 0;
+        int kpos0 = (rk.ish == wk[0]) ? 2 : 3;
+        if (wk[0] == wk[1]) kpos0 = 2;
+        const int bpos1 = 1 - bpos0, kpos1 = 5 - kpos0;
+        if (!swap) { pos[0] = bpos0; pos[1] = bpos1; pos[2] = kpos0; pos[3] = kpos1; }
+        else { pos[2] = bpos0; pos[3] = bpos1; pos[0] = kpos0; pos[1] = kpos1; }
+    }
+    (void)sh; (void)want;
+    const int oi = dims[pos[0]], oj = dims[pos[1]], ok = dims[pos[2]], ol = dims[pos[3]];
+    int strides[4] = {nj * nk * nl, nk * nl, nl, 1};
+    for (int a = 0; a < oi; ++a)
+        for (int b = 0; b < oj; ++b)
+            for (int c = 0; c < ok; ++c)
+                for (int d = 0; d < ol; ++d) {
+                    int idx[4];
+                    idx[pos[0]] = a; idx[pos[1]] = b; idx[pos[2]] = c; idx[pos[3]] = d;
+                    host_out[((a * oj + b) * ok + c) * ol + d] =
+                        blk[idx[0] * strides[0] + idx[1] * strides[1] + idx[2] * strides[2] + idx[3] * strides[3]];
+                }
+    return 0;
+}
+
+extern "C" int jk_rys_eval(int32_t n, const double *T, int32_t count, int32_t precision, double *roots, double *weights) {
+    if (n < 1 || n > JKT_RYS_NMAX || count < 0 || (count > 0 && (!T || !roots || !weights))) return fail(JK_EINVAL, "bad arguments");
+    if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
+    for (int i = 0; i < count; ++i)
+        if (!(std::isfinite(T[i]) && T[i] >= 0.0)) return fail(JK_EINVAL, "T must be finite and >= 0");
+    if (count == 0) return 0;
+    Tables tab;
+    int rc = tables_for_device(&tab);
+    if (rc) return rc;
+    double *dT, *du, *dw;
+    HIPCHK(hipMalloc(&dT, sizeof(double) * count));
+    HIPCHK(hipMalloc(&du, sizeof(double) * count * n));
+    HIPCHK(hipMalloc(&dw, sizeof(double) * count * n));
+    HIPCHK(hipMemcpy(dT, T, sizeof(double) * count, hipMemcpyHostToDevice));
+    const dim3 g((count + 127) / 128), b(128);
+#define RYS_CASE(N)                                                                                       \
+    case N:                                                                                               \
+        if (precision == JK_FP64) hipLaunchKernelGGL((k_rys_eval<N, double>), g, b, 0, 0, tab, dT, count, du, dw); \
+        else hipLaunchKernelGGL((k_rys_eval<N, float>), g, b, 0, 0, tab, dT, count, du, dw);              \
+        break;
+    switch (n) { RYS_CASE(1) RYS_CASE(2) RYS_CASE(3) RYS_CASE(4) RYS_CASE(5) RYS_CASE(6) RYS_CASE(7) RYS_CASE(8) RYS_CASE(9) }
+#undef RYS_CASE
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(roots, du, sizeof(double) * count * n, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(weights, dw, sizeof(double) * count * n, hipMemcpyDeviceToHost));
+    (void)hipFree(dT); (void)hipFree(du); (void)hipFree(dw);
+    return 0;
+}
+
+extern "C" int jk_boys_eval(int32_t mmax, const double *T, int32_t count, int32_t precision, double *out) {
+    if (mmax != 1 || count < 0 || (count > 0 && (!T || !out))) return fail(JK_EINVAL, "bad arguments (m must be 1)");
+    if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
+    for (int i = 0; i < count; ++i)
+        if (!(std::isfinite(T[i]) && T[i] >= 0.0)) return fail(JK_EINVAL, "T must be finite and >= 0");
+    if (count == 0) return 0;
+    Tables tab;
+    int rc = tables_for_device(&tab);
+    if (rc) return rc;
+    double *dT, *dout;
+    HIPCHK(hipMalloc(&dT, sizeof(double) * count));
+    HIPCHK(hipMalloc(&dout, sizeof(double) * count * 2));
+    HIPCHK(hipMemcpy(dT, T, sizeof(double) * count, hipMemcpyHostToDevice));
+    if (precision == JK_FP64) hipLaunchKernelGGL((k_boys_eval<double>), dim3((count + 127) / 128), dim3(128), 0, 0, tab, dT, count, dout);
+    else hipLaunchKernelGGL((k_boys_eval<float>), dim3((count + 127) / 128), dim3(128), 0, 0, tab, dT, count, dout);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(out, dout, sizeof(double) * count * 2, hipMemcpyDeviceToHost));
+    (void)hipFree(dT); (void)hipFree(dout);
+    return 0;
+}
+
+// batched builds: see jk_batch.hip

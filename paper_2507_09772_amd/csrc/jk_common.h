@@ -1,0 +1,103 @@
+// jk_common.h -- data layouts shared by the host planner and the kernels.
+#pragma once
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#define JK_HD __host__ __device__
+#else
+#define JK_HD
+#endif
+
+namespace jk {
+
+constexpr int LMAX = 4;
+constexpr int NCLS = (LMAX + 1) * (LMAX + 1) * (LMAX + 1) * (LMAX + 1);
+
+JK_HD constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+JK_HD constexpr int nroots(int li, int lj, int lk, int ll) { return (li + lj + lk + ll) / 2 + 1; }
+JK_HD constexpr int class_id(int li, int lj, int lk, int ll) { return ((li * (LMAX + 1) + lj) * (LMAX + 1) + lk) * (LMAX + 1) + ll; }
+
+// Cartesian exponent of component idx of a shell with angular momentum l
+// along axis (0 x, 1 y, 2 z); reversed lexicographic order.
+JK_HD constexpr int cart_comp(int l, int idx, int axis) {
+    int n = 0;
+    for (int x = l; x >= 0; --x)
+        for (int y = l - x; y >= 0; --y) {
+            if (n == idx) return axis == 0 ? x : (axis == 1 ? y : l - x - y);
+            ++n;
+        }
+    return 0;
+}
+
+// One oriented shell pair (I, J): the first shell has the higher (l, nprim)
+// type.  64 bytes.
+struct PairRec {
+    int32_t ish, jsh;      // shell indices
+    int32_t aoi, aoj;      // Cartesian AO offsets
+    int32_t pp_off, npp;   // primitive-pair range
+    int32_t pad0, pad1;
+    double ab[3];          // A - B
+    double q;              // Schwarz factor sqrt(max |(ab|ab)|)
+};
+
+// One primitive pair (a on A, b on B).  80 bytes.
+struct PrimPair {
+    double p;       // a + b
+    double h;       // 1 / (2p)
+    double kp;      // c_a c_b exp(-ab/p |AB|^2) / p
+    double pad;
+    double P[3];    // (a A + b B) / p
+    double PA[3];   // P - A
+};
+
+// Kernel family per angular class.
+//   1: one lane per quartet (register-resident integral block);
+//   2: a lane group per quartet, 2-D integrals staged in LDS.
+JK_HD constexpr int family(int li, int lj, int lk, int ll) {
+    return ncart(li) * ncart(lj) * ncart(lk) * ncart(ll) <= 36 ? 1 : 2;
+}
+// Family 2: lanes per quartet = ncart(li) * ncart(lk) (slot = (a, c)).
+JK_HD constexpr int k2_slots(int li, int lj, int lk, int ll) { return ncart(li) * ncart(lk); }
+JK_HD constexpr int k2_qw(int li, int lj, int lk, int ll) {
+    return k2_slots(li, lj, lk, ll) >= 64 ? 1 : 64 / k2_slots(li, lj, lk, ll);
+}
+// Quartets per wave-tile.
+JK_HD constexpr int quartets_per_tile(int li, int lj, int lk, int ll) {
+    return family(li, lj, lk, ll) == 1 ? 64 : k2_qw(li, lj, lk, ll);
+}
+
+enum { MODE_JK = 0, MODE_EXPORT = 1 };
+enum { SEL_ALL = 0, SEL_HIGH = 1, SEL_LOW = 2 };
+
+struct Tables {
+    const double *rys;     // degree-major Rys fits, FP64
+    const float *rys32;    // same, FP32
+    const double *hx2, *hw;  // large-T Gauss-Hermite limit
+    const float *hx2_32, *hw32;
+    const double *boys;    // F_m on the T grid
+    const float *boys32;
+};
+
+struct JkArgs {
+    const PairRec *pairs;
+    const PrimPair *pp;
+    // JK mode: tiles over (bra list position, ket chunk)
+    const int32_t *bra_list, *ket_list, *bra_cnt, *tile_off;
+    int32_t nbra, ntiles, same, npb, npk;
+    // EXPORT mode: explicit quartets
+    const int32_t *q_bra, *q_ket;
+    int32_t nq;
+    double *out;
+    // densities and results (Cartesian, [nset][nao][nao])
+    const double *D;
+    double *J, *K;
+    int64_t mstride;
+    int32_t nao, nset, do_j, do_k;
+    // precision split
+    const float *dmax;   // [nshell][nshell] max |D| over the block and densities
+    int32_t nshell, sel;
+    double mix_thr;
+    Tables tab;
+};
+
+}  // namespace jk

@@ -1,0 +1,762 @@
+// jk_device.h -- device math and the two J/K kernel families for gfx950.
+//
+// Integral method: Rys quadrature (paper Section 2).  For a primitive
+// quartet with exponents a, b, c, d on centres A, B, C, D, p = a + b,
+// q = c + d, P and Q the Gaussian product centres and T = pq/(p+q)|PQ|^2:
+//
+//   (ab|cd) = 2 pi^(5/2) / (p q sqrt(p+q)) K_AB K_CD
+//             sum_r w_r I_x(r) I_y(r) I_z(r)                       (eq. rys1)
+//
+// with N_r = floor((li+lj+lk+ll)/2) + 1 roots u_r = t_r^2 and weights w_r of
+// the Rys polynomials of order N_r at T, and per-direction 2-D integrals
+// I_x(a_x, b_x, c_x, d_x) (eq. rys2) built by the vertical recurrence
+//
+//   G(n+1, m) = C00 G(n, m) + n B10 G(n-1, m) + m B00 G(n, m-1)
+//   G(n, m+1) = C00' G(n, m) + m B01 G(n, m-1) + n B00 G(n-1, m)
+//   B00 = u / (2(p+q)),  B10 = (1 - q u/(p+q)) / (2p),  B01 = (1 - p u/(p+q)) / (2q)
+//   C00 = (P - A) - q u/(p+q) (P - Q),  C00' = (Q - C) + p u/(p+q) (P - Q)
+//
+// then horizontal transfer I(a, b+1) = I(a+1, b) + (A - B) I(a, b) on the
+// bra and likewise with (C - D) on the ket.
+//
+// J/K digestion (Section 2, eq. jk, over unique quartets): a unique shell
+// quartet with degeneracy weight w = 2^-[I=J] 2^-[K=L] 2^-[IJ=KL] feeds
+//   J'_ab += 2w v D_cd,  J'_cd += 2w v D_ab,
+//   K'_ac += w v D_bd,  K'_ad += w v D_bc,  K'_bc += w v D_ad,  K'_bd += w v D_ac,
+// and J = J' + J'^T, K = K' + K'^T afterwards (finalize kernel).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "jk_common.h"
+#include "tables/jk_tables_meta.h"
+
+namespace jk {
+
+constexpr double TWO_PI_2_5 = 34.986836655249725;  // 2 pi^(5/2)
+constexpr double SQRT_PI_HALF = 0.88622692545275801;  // sqrt(pi) / 2
+
+template <typename R> __device__ __forceinline__ R rsqrt_(R x);
+template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __frsqrt_rn(x); }
+
+template <typename R> struct TabSel;
+template <> struct TabSel<double> {
+    static __device__ __forceinline__ const double *rys(const Tables &t) { return t.rys; }
+    static __device__ __forceinline__ const double *hx2(const Tables &t) { return t.hx2; }
+    static __device__ __forceinline__ const double *hw(const Tables &t) { return t.hw; }
+    static __device__ __forceinline__ const double *boys(const Tables &t) { return t.boys; }
+};
+template <> struct TabSel<float> {
+    static __device__ __forceinline__ const float *rys(const Tables &t) { return t.rys32; }
+    static __device__ __forceinline__ const float *hx2(const Tables &t) { return t.hx2_32; }
+    static __device__ __forceinline__ const float *hw(const Tables &t) { return t.hw32; }
+    static __device__ __forceinline__ const float *boys(const Tables &t) { return t.boys32; }
+};
+
+// ---------------------------------------------------------------------------
+// One-root case: Boys function by Taylor expansion of the tabulated F_1 and
+// downward recursion F_0 = 2T F_1 + exp(-T); u = F_1 / F_0, w = F_0.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u, R &w) {
+    if (T < JKT_BOYS_TMAX) {
+        const int j = (int)(T * JKT_BOYS_DENSITY + 0.5);
+        const R d = (R)((double)j * (1.0 / JKT_BOYS_DENSITY) - T);  // T_j - T
+        const R *row = boys + j * (JKT_BOYS_MMAX + 1);
+        constexpr int NT = sizeof(R) == 8 ? 7 : 4;  // Taylor terms
+        R f1 = row[NT];
+#pragma unroll
+        for (int k = NT - 1; k >= 1; --k) f1 = row[k] + f1 * d * (R)(1.0 / k);
+        const R tt = (R)T;
+        R e;
+        if constexpr (sizeof(R) == 8) e = exp(-T);
+        else e = __expf(-tt);
+        const R f0 = (R)2 * tt * f1 + e;
+        w = f0;
+        u = f1 / f0;
+    } else {
+        const R rt = rsqrt_<R>((R)T);
+        w = (R)SQRT_PI_HALF * rt;
+        u = (R)0.5 / (R)T;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// N >= 2 roots: piecewise polynomial fits on unit intervals of T (Horner on
+// all 2N functions at once, degree-major layout), large-T Gauss-Hermite limit.
+// ---------------------------------------------------------------------------
+template <int N, typename R>
+__device__ __forceinline__ void rys_roots(double T, const Tables &tab, R (&u)[N], R (&w)[N]) {
+    if constexpr (N == 1) {
+        rys1<R>(T, TabSel<R>::boys(tab), u[0], w[0]);
+    } else {
+        static_assert(jkt_rys_h[N] == 1.0, "unit intervals assumed");
+        constexpr int NF = 2 * N;
+        if (T < jkt_rys_tmax[N]) {
+            const int it = (int)T;
+            const R x = (R)(2.0 * (T - (double)it) - 1.0);
+            const R *c = TabSel<R>::rys(tab) + jkt_rys_offset[N] + (it * (JKT_RYS_DEG + 1) + JKT_RYS_DEG) * NF;
+            R acc[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[f] = c[f];
+#pragma unroll
+            for (int k = JKT_RYS_DEG - 1; k >= 0; --k) {
+                c -= NF;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) acc[f] = acc[f] * x + c[f];
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                u[i] = acc[i];
+                w[i] = acc[N + i];
+            }
+        } else {
+            const R rT = (R)(1.0 / T);
+            const R rt = rsqrt_<R>((R)T);
+            const R *hx = TabSel<R>::hx2(tab) + jkt_herm_offset[N];
+            const R *hw = TabSel<R>::hw(tab) + jkt_herm_offset[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                u[i] = hx[i] * rT;
+                w[i] = hw[i] * rt;
+            }
+        }
+    }
+}
+
+// single root r of an N-root rule (the 2-D table builders of family 2)
+template <int N, typename R>
+__device__ __forceinline__ void rys_root1(double T, int r, const Tables &tab, R &u, R &w) {
+    if constexpr (N == 1) {
+        rys1<R>(T, TabSel<R>::boys(tab), u, w);
+    } else {
+        constexpr int NF = 2 * N;
+        if (T < jkt_rys_tmax[N]) {
+            const int it = (int)T;
+            const R x = (R)(2.0 * (T - (double)it) - 1.0);
+            const R *c = TabSel<R>::rys(tab) + jkt_rys_offset[N] + (it * (JKT_RYS_DEG + 1) + JKT_RYS_DEG) * NF;
+            R au = c[r], aw = c[N + r];
+#pragma unroll
+            for (int k = JKT_RYS_DEG - 1; k >= 0; --k) {
+                c -= NF;
+                au = au * x + c[r];
+                aw = aw * x + c[N + r];
+            }
+            u = au;
+            w = aw;
+        } else {
+            u = TabSel<R>::hx2(tab)[jkt_herm_offset[N] + r] * (R)(1.0 / T);
+            w = TabSel<R>::hw(tab)[jkt_herm_offset[N] + r] * rsqrt_<R>((R)T);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2-D integrals of one direction for one root: vertical recurrence G(n, m)
+// scaled by s, then horizontal transfers; emit(a, b, c, d, value) receives
+// every I(a, b, c, d), a <= LI, b <= LJ, c <= LK, d <= LL, in b-major order.
+// ---------------------------------------------------------------------------
+template <int LI, int LJ, int LK, int LL, typename R, typename Emit>
+__device__ __forceinline__ void rys2d(R c00, R c00p, R b00, R b10, R b01, R ab, R cd, R s, Emit &&emit) {
+    constexpr int NA = LI + LJ, NC = LK + LL;
+    R G[NA + 1][NC + 1];
+    G[0][0] = s;
+    if constexpr (NA > 0) G[1][0] = c00 * s;
+#pragma unroll
+    for (int n = 1; n < NA; ++n) G[n + 1][0] = c00 * G[n][0] + (R)n * b10 * G[n - 1][0];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+#pragma unroll
+        for (int n = 0; n <= NA; ++n) {
+            R v = c00p * G[n][m];
+            if (m > 0) v += (R)m * b01 * G[n][m - 1];
+            if (n > 0) v += (R)n * b00 * G[n - 1][m];
+            G[n][m + 1] = v;
+        }
+    }
+    // bra transfer, one b level at a time; X[a][m] holds level b for a <= NA - b
+    R X[NA + 1][NC + 1];
+#pragma unroll
+    for (int n = 0; n <= NA; ++n)
+#pragma unroll
+        for (int m = 0; m <= NC; ++m) X[n][m] = G[n][m];
+#pragma unroll
+    for (int b = 0; b <= LJ; ++b) {
+        if (b > 0) {
+#pragma unroll
+            for (int n = 0; n <= NA - b; ++n)
+#pragma unroll
+                for (int m = 0; m <= NC; ++m) X[n][m] = X[n + 1][m] + ab * X[n][m];
+        }
+#pragma unroll
+        for (int a = 0; a <= LI; ++a) {
+            // ket transfer on X[a][0..NC]
+            R Y[NC + 1];
+#pragma unroll
+            for (int m = 0; m <= NC; ++m) Y[m] = X[a][m];
+#pragma unroll
+            for (int d = 0; d <= LL; ++d) {
+                if (d > 0) {
+#pragma unroll
+                    for (int c = 0; c <= NC - d; ++c) Y[c] = Y[c + 1] + cd * Y[c];
+                }
+#pragma unroll
+                for (int c = 0; c <= LK; ++c) emit(a, b, c, d, Y[c]);
+            }
+        }
+    }
+}
+
+template <int LI, int LJ, int LK, int LL>
+struct Cls {
+    static constexpr int NI = ncart(LI), NJ = ncart(LJ), NK = ncart(LK), NL = ncart(LL);
+    static constexpr int NAB = NI * NJ, NCD = NK * NL, NC = NAB * NCD;
+    static constexpr int NR = nroots(LI, LJ, LK, LL);
+    static constexpr int S = (LI + 1) * (LJ + 1) * (LK + 1) * (LL + 1);
+    // index of I(a, b, c, d) in a [a][b][c][d] table
+    static __device__ __forceinline__ constexpr int t4(int a, int b, int c, int d) {
+        return ((a * (LJ + 1) + b) * (LK + 1) + c) * (LL + 1) + d;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void atomic_add_f64(double *p, T v) {
+    unsafeAtomicAdd(p, (double)v);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Largest i in [0, n) with off[i] <= key (off ascending, off[0] = 0).
+__device__ __forceinline__ int tile_bra(const int32_t *__restrict__ off, int n, int key) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= key) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float dmax6(const JkArgs &a, const PairRec &B, const PairRec &K) {
+    const float *dm = a.dmax;
+    const int n = a.nshell;
+    float m = dm[B.ish * n + B.jsh];
+    m = fmaxf(m, dm[K.ish * n + K.jsh]);
+    m = fmaxf(m, dm[B.ish * n + K.ish]);
+    m = fmaxf(m, dm[B.ish * n + K.jsh]);
+    m = fmaxf(m, dm[B.jsh * n + K.ish]);
+    m = fmaxf(m, dm[B.jsh * n + K.jsh]);
+    return m;
+}
+
+__device__ __forceinline__ bool selected(const JkArgs &a, const PairRec &B, const PairRec &K) {
+    if (a.sel == SEL_ALL) return true;
+    const double bound = B.q * K.q * (double)dmax6(a, B, K);
+    return a.sel == SEL_HIGH ? bound >= a.mix_thr : bound < a.mix_thr;
+}
+
+// Geometry of one primitive quartet.  Differences of centres are formed in
+// FP64 and rounded to R afterwards.
+template <typename R>
+struct PQuart {
+    double T;
+    R fq, fp, rpq, pref, hb, hk;
+    R PQ[3], PA[3], QC[3];
+};
+
+template <typename R>
+__device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const PrimPair &pk) {
+    PQuart<R> g;
+    const double p = pb.p, q = pk.p;
+    const double rpq = 1.0 / (p + q);
+    double pq2 = 0.0, d[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        d[x] = pb.P[x] - pk.P[x];
+        pq2 += d[x] * d[x];
+    }
+    g.T = p * q * rpq * pq2;
+    g.rpq = (R)rpq;
+    g.fq = (R)(q * rpq);
+    g.fp = (R)(p * rpq);
+    g.pref = (R)(TWO_PI_2_5 * pb.kp * pk.kp * sqrt(rpq));
+    g.hb = (R)pb.h;
+    g.hk = (R)pk.h;
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        g.PQ[x] = (R)d[x];
+        g.PA[x] = (R)pb.PA[x];
+        g.QC[x] = (R)pk.PA[x];
+    }
+    return g;
+}
+
+// ===========================================================================
+// Family 1: one lane per quartet.  The contracted Cartesian block V lives in
+// registers; digestion reduces J_IJ across the wave (the bra is uniform in a
+// tile) and sends the other five blocks straight to FP64 atomics.
+// ===========================================================================
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+__global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
+    using C = Cls<LI, LJ, LK, LL>;
+    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NAB = C::NAB, NCD = C::NCD, NR = C::NR;
+    const int lane = threadIdx.x & 63;
+    int bra, ket;
+    bool valid;
+    double wq = 1.0;
+    if constexpr (MODE == MODE_JK) {
+        const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+        if (wave >= a.ntiles) return;
+        const int i = tile_bra(a.tile_off, a.nbra, wave);
+        const int j = (wave - a.tile_off[i]) * 64 + lane;
+        const int cnt = a.bra_cnt[i];
+        valid = j < cnt;
+        bra = a.bra_list[i];
+        ket = a.ket_list[valid ? j : cnt - 1];
+        if (a.same && j == i) wq *= 0.5;
+    } else {
+        const int g = blockIdx.x * 256 + threadIdx.x;
+        valid = g < a.nq;
+        const int gg = valid ? g : a.nq - 1;
+        bra = a.q_bra[gg];
+        ket = a.q_ket[gg];
+    }
+    const PairRec B = a.pairs[bra];
+    const PairRec Kt = a.pairs[ket];
+    if constexpr (MODE == MODE_JK) {
+        if (B.ish == B.jsh) wq *= 0.5;
+        if (Kt.ish == Kt.jsh) wq *= 0.5;
+        valid = valid && selected(a, B, Kt);
+    }
+    R V[NAB * NCD];
+#pragma unroll
+    for (int e = 0; e < NAB * NCD; ++e) V[e] = (R)0;
+    const int npb = MODE == MODE_JK ? a.npb : B.npp;
+    const int npk = MODE == MODE_JK ? a.npk : Kt.npp;
+    const R ab[3] = {(R)B.ab[0], (R)B.ab[1], (R)B.ab[2]};
+    const R cd[3] = {(R)Kt.ab[0], (R)Kt.ab[1], (R)Kt.ab[2]};
+    for (int ib = 0; ib < npb; ++ib) {
+        const PrimPair pb = a.pp[B.pp_off + ib];
+        for (int ik = 0; ik < npk; ++ik) {
+            const PrimPair pk = a.pp[Kt.pp_off + ik];
+            const PQuart<R> g = prim_quartet<R>(pb, pk);
+            R u[NR], w[NR];
+            rys_roots<NR, R>(g.T, a.tab, u, w);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const R t = u[r];
+                const R b00 = (R)0.5 * t * g.rpq;
+                const R b10 = g.hb * ((R)1 - g.fq * t);
+                const R b01 = g.hk * ((R)1 - g.fp * t);
+                R I[3][C::S];
+#pragma unroll
+                for (int x = 0; x < 3; ++x) {
+                    const R c00 = g.PA[x] - g.fq * t * g.PQ[x];
+                    const R c00p = g.QC[x] + g.fp * t * g.PQ[x];
+                    const R s = x == 2 ? w[r] * g.pref : (R)1;
+                    R *dst = I[x];
+                    rys2d<LI, LJ, LK, LL, R>(c00, c00p, b00, b10, b01, ab[x], cd[x], s,
+                                             [&](int ia, int ib2, int ic, int id, R v) { dst[C::t4(ia, ib2, ic, id)] = v; });
+                }
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                        for (int k = 0; k < NK; ++k)
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) {
+                                const int ix = C::t4(cart_comp(LI, i, 0), cart_comp(LJ, j, 0), cart_comp(LK, k, 0), cart_comp(LL, l, 0));
+                                const int iy = C::t4(cart_comp(LI, i, 1), cart_comp(LJ, j, 1), cart_comp(LK, k, 1), cart_comp(LL, l, 1));
+                                const int iz = C::t4(cart_comp(LI, i, 2), cart_comp(LJ, j, 2), cart_comp(LK, k, 2), cart_comp(LL, l, 2));
+                                V[((i * NJ + j) * NK + k) * NL + l] += I[0][ix] * I[1][iy] * I[2][iz];
+                            }
+            }
+        }
+    }
+    if constexpr (MODE == MODE_EXPORT) {
+        if (valid) {
+            const int g = blockIdx.x * 256 + threadIdx.x;
+            double *o = a.out + (int64_t)g * (NAB * NCD);
+#pragma unroll
+            for (int e = 0; e < NAB * NCD; ++e) o[e] = (double)V[e];
+        }
+        return;
+    } else {
+        const int n = a.nao;
+        for (int s = 0; s < a.nset; ++s) {
+            const double *D = a.D + s * a.mstride;
+            double *Jm = a.J + s * a.mstride;
+            double *Km = a.K + s * a.mstride;
+            if (a.do_j) {
+                double dij[NAB], dkl[NCD];
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) dij[i * NJ + j] = D[(B.aoi + i) * n + B.aoj + j];
+#pragma unroll
+                for (int k = 0; k < NK; ++k)
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) dkl[k * NL + l] = D[(Kt.aoi + k) * n + Kt.aoj + l];
+                const double w2 = valid ? 2.0 * wq : 0.0;
+                // J_IJ: reduce over the wave's kets
+                double mine = 0.0;
+#pragma unroll
+                for (int ab2 = 0; ab2 < NAB; ++ab2) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
+                    s2 = wave_sum(s2 * w2);
+                    if (lane == ab2) mine = s2;
+                }
+                if (lane < NAB) atomic_add_f64(&Jm[(B.aoi + lane / NJ) * n + B.aoj + lane % NJ], mine);
+                if (valid) {
+#pragma unroll
+                    for (int cd2 = 0; cd2 < NCD; ++cd2) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int ab2 = 0; ab2 < NAB; ++ab2) s2 += (double)V[ab2 * NCD + cd2] * dij[ab2];
+                        atomic_add_f64(&Jm[(Kt.aoi + cd2 / NL) * n + Kt.aoj + cd2 % NL], w2 * s2);
+                    }
+                }
+            }
+            if (a.do_k && valid) {
+                double djl[NJ * NL], djk[NJ * NK], dil[NI * NL], dik[NI * NK];
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) djl[j * NL + l] = D[(B.aoj + j) * n + Kt.aoj + l];
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) djk[j * NK + k] = D[(B.aoj + j) * n + Kt.aoi + k];
+                }
+#pragma unroll
+                for (int i = 0; i < NI; ++i) {
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) dil[i * NL + l] = D[(B.aoi + i) * n + Kt.aoj + l];
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) dik[i * NK + k] = D[(B.aoi + i) * n + Kt.aoi + k];
+                }
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * djl[j * NL + l];
+                        atomic_add_f64(&Km[(B.aoi + i) * n + Kt.aoi + k], wq * s2);
+                    }
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                            for (int k = 0; k < NK; ++k) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * djk[j * NK + k];
+                        atomic_add_f64(&Km[(B.aoi + i) * n + Kt.aoj + l], wq * s2);
+                    }
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int i = 0; i < NI; ++i)
+#pragma unroll
+                            for (int l = 0; l < NL; ++l) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * dil[i * NL + l];
+                        atomic_add_f64(&Km[(B.aoj + j) * n + Kt.aoi + k], wq * s2);
+                    }
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int i = 0; i < NI; ++i)
+#pragma unroll
+                            for (int k = 0; k < NK; ++k) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * dik[i * NK + k];
+                        atomic_add_f64(&Km[(B.aoj + j) * n + Kt.aoj + l], wq * s2);
+                    }
+            }
+        }
+    }
+}
+
+// ===========================================================================
+// Family 2: a lane group per quartet.  Lane slot (a, c) owns the elements
+// (a b | c d) for all b in the current pass's chunk and all d.  Per
+// primitive quartet, lanes build the 2-D tables I_x, I_y, I_z of every root
+// into LDS (one task = one root and direction), then every slot accumulates
+// its elements from LDS.  Digestion: per slot partial sums, reduced across
+// the group with LDS atomics, then one FP64 global atomic per block element.
+// ===========================================================================
+template <int LI, int LJ, int LK, int LL>
+struct K2Cfg {
+    using C = Cls<LI, LJ, LK, LL>;
+    static constexpr int NSLOT = C::NI * C::NK;
+    static constexpr int QW = k2_qw(LI, LJ, LK, LL);
+    static constexpr int LPQ = QW > 1 ? NSLOT : 64;          // lanes per quartet
+    static constexpr int SPL = (NSLOT + LPQ - 1) / LPQ;       // slots per lane
+    // b-chunk per pass: keep SPL * CB * NL accumulators <= 48
+    static constexpr int cb_() {
+        int cb = C::NJ;
+        while (cb > 1 && SPL * cb * C::NL > 48) --cb;
+        return cb;
+    }
+    static constexpr int CB = cb_();
+    static constexpr int NPASS = (C::NJ + CB - 1) / CB;
+    static constexpr int TAB = C::NR * 3 * C::S;              // 2-D table entries per quartet
+    // LDS digestion blocks: jij, jkl, kik, kil, kjk, kjl
+    static constexpr int O_JIJ = 0;
+    static constexpr int O_JKL = O_JIJ + C::NI * C::NJ;
+    static constexpr int O_KIK = O_JKL + C::NK * C::NL;
+    static constexpr int O_KIL = O_KIK + C::NI * C::NK;
+    static constexpr int O_KJK = O_KIL + C::NI * C::NL;
+    static constexpr int O_KJL = O_KJK + C::NJ * C::NK;
+    static constexpr int DIG = O_KJL + C::NJ * C::NL;
+    // table index [ax][cx][bx][dx]
+    static __device__ __forceinline__ constexpr int tix(int ax, int bx, int cx, int dx) {
+        return ((ax * (LK + 1) + cx) * (LJ + 1) + bx) * (LL + 1) + dx;
+    }
+};
+
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+__global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
+    using C = Cls<LI, LJ, LK, LL>;
+    using F = K2Cfg<LI, LJ, LK, LL>;
+    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, S = C::S;
+    constexpr int QW = F::QW, LPQ = F::LPQ, SPL = F::SPL, CB = F::CB, NPASS = F::NPASS;
+    __shared__ R tabs[QW * F::TAB];
+    __shared__ double dig[QW * F::DIG];
+
+    const int lane = threadIdx.x;
+    const int q = QW > 1 ? lane / LPQ : 0;          // quartet of this lane
+    const int sl = QW > 1 ? lane % LPQ : lane;      // lane index within its quartet
+    const bool lane_used = q < QW;                  // lanes beyond QW*LPQ idle
+    const int qq = lane_used ? q : 0;
+
+    int bra, ket;
+    bool valid;
+    double wq = 1.0;
+    int gq;  // export slot
+    if constexpr (MODE == MODE_JK) {
+        const int wave = blockIdx.x;
+        const int i = tile_bra(a.tile_off, a.nbra, wave);
+        const int j = (wave - a.tile_off[i]) * QW + qq;
+        const int cnt = a.bra_cnt[i];
+        valid = lane_used && j < cnt;
+        bra = a.bra_list[i];
+        ket = a.ket_list[j < cnt ? j : cnt - 1];
+        if (a.same && j == i) wq *= 0.5;
+        gq = 0;
+    } else {
+        gq = blockIdx.x * QW + qq;
+        valid = lane_used && gq < a.nq;
+        const int gg = gq < a.nq ? gq : a.nq - 1;
+        bra = a.q_bra[gg];
+        ket = a.q_ket[gg];
+    }
+    const PairRec B = a.pairs[bra];
+    const PairRec Kt = a.pairs[ket];
+    if constexpr (MODE == MODE_JK) {
+        if (B.ish == B.jsh) wq *= 0.5;
+        if (Kt.ish == Kt.jsh) wq *= 0.5;
+        valid = valid && selected(a, B, Kt);
+    }
+    const int npb = MODE == MODE_JK ? a.npb : B.npp;
+    const int npk = MODE == MODE_JK ? a.npk : Kt.npp;
+    const int npq = npb * npk;  // per quartet; uniform within a wave in JK mode
+    // the wave loops over the largest primitive count among its quartets
+    int npq_max = npq;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) npq_max = max(npq_max, __shfl_xor(npq_max, off, 64));
+
+    R *tq = tabs + qq * F::TAB;
+    double *dq = dig + qq * F::DIG;
+
+    // slot coordinates
+    int sa[SPL], sc[SPL];
+    bool sv[SPL];
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+        const int slot = sl + k * LPQ;
+        sv[k] = lane_used && slot < F::NSLOT;
+        const int s2 = sv[k] ? slot : 0;
+        sa[k] = s2 / NK;
+        sc[k] = s2 % NK;
+    }
+    int base[SPL][3];
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+        // runtime (a, c) -> Cartesian exponents via small switch-free loops
+        int ae[3] = {0, 0, 0}, ce[3] = {0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < NI; ++t)
+            if (t == sa[k]) { ae[0] = cart_comp(LI, t, 0); ae[1] = cart_comp(LI, t, 1); ae[2] = cart_comp(LI, t, 2); }
+#pragma unroll
+        for (int t = 0; t < NK; ++t)
+            if (t == sc[k]) { ce[0] = cart_comp(LK, t, 0); ce[1] = cart_comp(LK, t, 1); ce[2] = cart_comp(LK, t, 2); }
+#pragma unroll
+        for (int x = 0; x < 3; ++x) base[k][x] = x * S + F::tix(ae[x], 0, ce[x], 0);
+    }
+    const R ab[3] = {(R)B.ab[0], (R)B.ab[1], (R)B.ab[2]};
+    const R cd[3] = {(R)Kt.ab[0], (R)Kt.ab[1], (R)Kt.ab[2]};
+
+#pragma unroll
+    for (int pass = 0; pass < NPASS; ++pass) {
+        R acc[SPL][CB][NL];
+#pragma unroll
+        for (int k = 0; k < SPL; ++k)
+#pragma unroll
+            for (int bb = 0; bb < CB; ++bb)
+#pragma unroll
+                for (int d = 0; d < NL; ++d) acc[k][bb][d] = (R)0;
+
+        for (int ipq = 0; ipq < npq_max; ++ipq) {
+            const bool has = ipq < npq;
+            const int ib = has ? ipq / npk : 0, ik = has ? ipq % npk : 0;
+            // tables are rebuilt per pass only when there is more than one
+            // primitive quartet in the wave; otherwise pass 0's survive
+            const bool build = pass == 0 || npq_max > 1;
+            if (build) {
+                if (pass > 0 || ipq > 0) __syncthreads();
+                const PrimPair pb = a.pp[B.pp_off + ib];
+                const PrimPair pk = a.pp[Kt.pp_off + ik];
+                const PQuart<R> g = prim_quartet<R>(pb, pk);
+                for (int t = sl; t < 3 * NR && lane_used; t += LPQ) {
+                    const int r = t / 3, x = t % 3;
+                    R u, w;
+                    rys_root1<NR, R>(g.T, r, a.tab, u, w);
+                    const R b00 = (R)0.5 * u * g.rpq;
+                    const R b10 = g.hb * ((R)1 - g.fq * u);
+                    const R b01 = g.hk * ((R)1 - g.fp * u);
+                    R pqx = g.PQ[0], pax = g.PA[0], qcx = g.QC[0], abx = ab[0], cdx = cd[0];
+                    if (x == 1) { pqx = g.PQ[1]; pax = g.PA[1]; qcx = g.QC[1]; abx = ab[1]; cdx = cd[1]; }
+                    if (x == 2) { pqx = g.PQ[2]; pax = g.PA[2]; qcx = g.QC[2]; abx = ab[2]; cdx = cd[2]; }
+                    const R c00 = pax - g.fq * u * pqx;
+                    const R c00p = qcx + g.fp * u * pqx;
+                    const R sc2 = x == 2 ? (has ? w * g.pref : (R)0) : (R)1;
+                    R *dst = tq + (r * 3 + x) * S;
+                    rys2d<LI, LJ, LK, LL, R>(c00, c00p, b00, b10, b01, abx, cdx, sc2,
+                                             [&](int ia, int ib2, int ic, int id, R v) { dst[F::tix(ia, ib2, ic, id)] = v; });
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const R *tr = tq + r * 3 * S;
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+#pragma unroll
+                    for (int bb = 0; bb < CB; ++bb) {
+                        const int b = pass * CB + bb;
+                        if (b >= NJ) continue;
+#pragma unroll
+                        for (int d = 0; d < NL; ++d) {
+                            const int ox = F::tix(0, cart_comp(LJ, b, 0), 0, cart_comp(LL, d, 0));
+                            const int oy = F::tix(0, cart_comp(LJ, b, 1), 0, cart_comp(LL, d, 1));
+                            const int oz = F::tix(0, cart_comp(LJ, b, 2), 0, cart_comp(LL, d, 2));
+                            acc[k][bb][d] += tr[base[k][0] + ox] * tr[base[k][1] + oy] * tr[base[k][2] + oz];
+                        }
+                    }
+                }
+            }
+        }
+
+        if constexpr (MODE == MODE_EXPORT) {
+#pragma unroll
+            for (int k = 0; k < SPL; ++k) {
+                if (!(valid && sv[k])) continue;
+                double *o = a.out + (int64_t)gq * C::NC;
+#pragma unroll
+                for (int bb = 0; bb < CB; ++bb) {
+                    const int b = pass * CB + bb;
+                    if (b >= NJ) continue;
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) o[((sa[k] * NJ + b) * NK + sc[k]) * NL + d] = (double)acc[k][bb][d];
+                }
+            }
+        } else {
+            const int n = a.nao;
+            for (int s = 0; s < a.nset; ++s) {
+                const double *D = a.D + s * a.mstride;
+                __syncthreads();
+                for (int t = lane; t < QW * F::DIG; t += 64) dig[t] = 0.0;
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < SPL; ++k) {
+                    if (!(valid && sv[k])) continue;
+                    const int ia = sa[k], ic = sc[k];
+                    const int ga = B.aoi + ia, gc = Kt.aoi + ic;
+                    double dkl[NL], dil[NL];
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) {
+                        dkl[d] = D[gc * n + Kt.aoj + d];
+                        dil[d] = D[ga * n + Kt.aoj + d];
+                    }
+                    const double dik = D[ga * n + gc];
+                    double kik = 0.0, jkl[NL], kil[NL];
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) { jkl[d] = 0.0; kil[d] = 0.0; }
+#pragma unroll
+                    for (int bb = 0; bb < CB; ++bb) {
+                        const int b = pass * CB + bb;
+                        if (b >= NJ) continue;
+                        const int gb = B.aoj + b;
+                        const double dij = D[ga * n + gb];
+                        const double djk = D[gb * n + gc];
+                        double jij = 0.0, kjk = 0.0;
+#pragma unroll
+                        for (int d = 0; d < NL; ++d) {
+                            const double v = (double)acc[k][bb][d];
+                            const double djl = D[gb * n + Kt.aoj + d];
+                            jij += v * dkl[d];
+                            jkl[d] += v * dij;
+                            kik += v * djl;
+                            kil[d] += v * djk;
+                            kjk += v * dil[d];
+                            if (a.do_k) atomicAdd(&dq[F::O_KJL + b * NL + d], wq * v * dik);
+                        }
+                        if (a.do_j) atomicAdd(&dq[F::O_JIJ + ia * NJ + b], 2.0 * wq * jij);
+                        if (a.do_k) atomicAdd(&dq[F::O_KJK + b * NK + ic], wq * kjk);
+                    }
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) {
+                        if (a.do_j) atomicAdd(&dq[F::O_JKL + ic * NL + d], 2.0 * wq * jkl[d]);
+                        if (a.do_k) atomicAdd(&dq[F::O_KIL + ia * NL + d], wq * kil[d]);
+                    }
+                    if (a.do_k) atomicAdd(&dq[F::O_KIK + ia * NK + ic], wq * kik);
+                }
+                __syncthreads();
+                // flush the group's blocks to global memory
+                if (lane_used && valid) {
+                    double *Jm = a.J + s * a.mstride;
+                    double *Km = a.K + s * a.mstride;
+                    for (int t = sl; t < F::DIG; t += LPQ) {
+                        const double v = dq[t];
+                        if (v == 0.0) continue;
+                        int row, col;
+                        double *M;
+                        if (t < F::O_JKL) { row = B.aoi + t / NJ; col = B.aoj + t % NJ; M = Jm; }
+                        else if (t < F::O_KIK) { const int e = t - F::O_JKL; row = Kt.aoi + e / NL; col = Kt.aoj + e % NL; M = Jm; }
+                        else if (t < F::O_KIL) { const int e = t - F::O_KIK; row = B.aoi + e / NK; col = Kt.aoi + e % NK; M = Km; }
+                        else if (t < F::O_KJK) { const int e = t - F::O_KIL; row = B.aoi + e / NL; col = Kt.aoj + e % NL; M = Km; }
+                        else if (t < F::O_KJL) { const int e = t - F::O_KJK; row = B.aoj + e / NK; col = Kt.aoi + e % NK; M = Km; }
+                        else { const int e = t - F::O_KJL; row = B.aoj + e / NL; col = Kt.aoj + e % NL; M = Km; }
+                        atomic_add_f64(&M[row * n + col], v);
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace jk

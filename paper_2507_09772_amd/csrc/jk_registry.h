@@ -1,0 +1,21 @@
+// jk_registry.h -- per-class launchers filled in by the kern_bra units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "jk_device.h"
+
+namespace jk {
+
+constexpr int LMAX_BUILT = 3;  // classes instantiated up to (ff|ff)
+
+using Launcher = hipError_t (*)(const JkArgs &, hipStream_t);
+
+struct ClassEntry {
+    Launcher jk64, jk32, ex64, ex32;
+};
+
+// Indexed by class_id(li, lj, lk, ll); zero-initialised, filled by the
+// static initialisers of the kernel units when the library loads.
+extern ClassEntry g_classes[NCLS];
+
+}  // namespace jk

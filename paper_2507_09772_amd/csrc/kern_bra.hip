@@ -1,0 +1,50 @@
+// kern_bra.hip -- kernel instantiations for one bra angular pair (JK_LI, JK_LJ),
+// compiled once per pair with -DJK_LI=.. -DJK_LJ=.. so the classes build in
+// parallel.  Kets (LK, LL) run over every canonical pair with LK >= LL and
+// (LK, LL) <= (JK_LI, JK_LJ) lexicographically.
+#include "jk_registry.h"
+
+#ifndef JK_LI
+#error "JK_LI / JK_LJ must be defined"
+#endif
+
+namespace jk {
+
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+static hipError_t launch_one(const JkArgs &a, hipStream_t s) {
+    if constexpr (family(LI, LJ, LK, LL) == 1) {
+        const int grid = MODE == MODE_JK ? (a.ntiles + 3) / 4 : (a.nq + 255) / 256;
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL((jk_k1<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(256), 0, s, a);
+    } else {
+        constexpr int QW = k2_qw(LI, LJ, LK, LL);
+        const int grid = MODE == MODE_JK ? a.ntiles : (a.nq + QW - 1) / QW;
+        if (grid <= 0) return hipSuccess;
+        hipLaunchKernelGGL((jk_k2<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(64), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int LK, int LL>
+static void reg_one() {
+    constexpr int LI = JK_LI, LJ = JK_LJ;
+    if constexpr (LK >= LL && (LK < LI || (LK == LI && LL <= LJ))) {
+        ClassEntry &e = g_classes[class_id(LI, LJ, LK, LL)];
+        e.jk64 = &launch_one<LI, LJ, LK, LL, double, MODE_JK>;
+        e.jk32 = &launch_one<LI, LJ, LK, LL, float, MODE_JK>;
+        e.ex64 = &launch_one<LI, LJ, LK, LL, double, MODE_EXPORT>;
+        e.ex32 = &launch_one<LI, LJ, LK, LL, float, MODE_EXPORT>;
+    }
+}
+
+static int reg_all() {
+    reg_one<0, 0>();
+    reg_one<1, 0>(); reg_one<1, 1>();
+    reg_one<2, 0>(); reg_one<2, 1>(); reg_one<2, 2>();
+    reg_one<3, 0>(); reg_one<3, 1>(); reg_one<3, 2>(); reg_one<3, 3>();
+    return 0;
+}
+
+static const int registered = reg_all();
+
+}  // namespace jk

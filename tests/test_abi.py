@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/jk.h declares, and rejects bad input before touching
+the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_09772_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "jk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(jk_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def jkmod():
+    from paper_2507_09772_amd import jk
+    jk.lib()
+    return jk
+
+
+def test_exports_every_declared_symbol(jkmod):
+    names = _declared()
+    assert "jk_build" in names and "jk_execute" in names
+    for n in names:
+        assert hasattr(jkmod.lib(), n), n
+
+
+def _mol():
+    return synth.workload("c0").mol
+
+
+def _bad(**kw):
+    m = _mol()
+    d = dict(l=m.l.copy(), nprim=m.nprim.copy(), atom=m.atom.copy(), exps=m.exps.copy(), coefs=m.coefs.copy(),
+             coords=m.coords.copy(), spherical=m.spherical)
+    for k, v in kw.items():
+        d[k] = v(d[k]) if callable(v) else v
+    return synth.Molecule(**d)
+
+
+def _set(arr, i, v):
+    a = arr.copy()
+    a[i] = v
+    return a
+
+
+@pytest.mark.parametrize("mol,code", [
+    (lambda: _bad(l=lambda a: _set(a, 2, 9)), -1),
+    (lambda: _bad(l=lambda a: _set(a, 2, 4)), -2),
+    (lambda: _bad(nprim=lambda a: _set(a, 0, 0)), -1),
+    (lambda: _bad(atom=lambda a: _set(a, 1, 99)), -1),
+    (lambda: _bad(exps=lambda a: _set(a, 3, -1.0)), -1),
+    (lambda: _bad(exps=lambda a: _set(a, 3, np.nan)), -1),
+    (lambda: _bad(coefs=lambda a: _set(a, 0, np.inf)), -1),
+    (lambda: _bad(coords=lambda a: _set(a, (0, 1), np.nan)), -1),
+])
+def test_plan_validation(jkmod, mol, code):
+    with pytest.raises(jkmod.JKError) as e:
+        jkmod.Plan(mol())
+    assert e.value.code == code
+    assert jkmod.lib().jk_last_error()
+
+
+def test_bad_cutoff_and_null(jkmod):
+    with pytest.raises(jkmod.JKError) as e:
+        jkmod.Plan(_mol(), cutoff=-1.0)
+    assert e.value.code == -1
+    assert jkmod.lib().jk_plan_create(None, 1e-13, ctypes.byref(ctypes.c_void_p())) == -1
+    assert jkmod.lib().jk_execute(None, None, 1, 3, 0, 0.0, 0.0, None, None, None) == -1
+    assert jkmod.lib().jk_plan_info(None, None, None) == -1
+
+
+def test_rys_eval_validation(jkmod):
+    with pytest.raises(jkmod.JKError):
+        jkmod.rys_eval(0, [1.0])
+    with pytest.raises(jkmod.JKError):
+        jkmod.rys_eval(3, [-1.0])
+    with pytest.raises(jkmod.JKError):
+        jkmod.rys_eval(10, [1.0])

@@ -1,0 +1,220 @@
+"""GPU parity: the HIP J/K path (through the C ABI) against the CPU oracle.
+
+Tolerance: max elementwise |dJ|, |dK| <= 1e-10 in FP64; mixed precision
+within |dE_J|, |dE_K| <= 1e-6 Eh.  Inputs are the seeded synthetic
+workloads; at the full config sizes the oracle computes sampled blocks of
+J and K one by one from the definition.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as o
+from paper_2507_09772_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def jkmod(torch_cuda):
+    from paper_2507_09772_amd import jk
+    jk.lib()
+    return jk
+
+
+def run_gpu(jkmod, torch, wl, precision="fp64", plan=None, **kw):
+    plan = plan or jkmod.Plan(wl.mol, wl.cutoff)
+    D = torch.from_numpy(wl.D).cuda()
+    J, K = plan.execute(D, precision=precision, **kw)
+    torch.cuda.synchronize()
+    return plan, J.cpu().numpy(), K.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# tables as the kernels evaluate them
+# ---------------------------------------------------------------------------
+def _T_grid():
+    T = [0.0, 1e-14, 1e-9, 1e-4, 0.3, 0.5, 0.999999, 1.0, 1.5, 3.7, 9.999, 17.25, 25.0, 33.3, 38.99, 39.0,
+         39.01, 45.99, 46.0, 50.9, 51.0, 55.5, 60.5, 64.9, 68.99, 69.0, 72.5, 76.9, 77.0, 80.0, 150.0, 1e4]
+    return np.array(T + list(np.random.default_rng(0).uniform(0, 90, 200)))
+
+
+@pytest.mark.parametrize("n", range(1, 10))
+def test_rys_moment_identity(jkmod, n):
+    """sum_i w_i u_i^k = F_k(T), k = 0..2n-1 (Gauss quadrature exactness),
+    against the oracle's pinned Boys function."""
+    say("rys", n)
+    T = _T_grid()
+    for prec, tol in (("fp64", 3e-14), ("fp32", 3e-6)):
+        u, w = jkmod.rys_eval(n, T, prec)
+        assert np.all(u > 0) and np.all(u < 1) and np.all(w > 0)
+        for t, uu, ww in zip(T, u, w):
+            F = o.boys(2 * n - 1, float(t))
+            for k in range(2 * n):
+                lhs = float(np.sum(ww * uu ** k))
+                assert abs(lhs - F[k]) <= tol * F[k] + 1e-300, (prec, n, t, k, lhs, F[k])
+
+
+def test_boys_eval(jkmod):
+    say("boys")
+    T = _T_grid()
+    for prec, tol in (("fp64", 2e-15), ("fp32", 2e-6)):
+        out = jkmod.boys_eval(T, prec)
+        for t, (f0, f1) in zip(T, out):
+            F = o.boys(1, float(t))
+            assert abs(f0 - F[0]) <= tol * F[0]
+            assert abs(f1 - F[1]) <= 4 * tol * F[1]
+
+
+# ---------------------------------------------------------------------------
+# integral blocks and Schwarz factors
+# ---------------------------------------------------------------------------
+def _class_samples(mol, per_class=2, seed=0):
+    """Shell quartets covering every (li, lj, lk, ll) pattern present."""
+    rng = np.random.default_rng(seed)
+    ls = [int(x) for x in mol.l]
+    by = {}
+    ns = len(ls)
+    for _ in range(20000):
+        q = tuple(int(x) for x in rng.integers(0, ns, 4))
+        key = tuple(ls[x] for x in q)
+        by.setdefault(key, [])
+        if len(by[key]) < per_class:
+            by[key].append(q)
+    return [q for v in by.values() for q in v]
+
+
+@pytest.mark.parametrize("basis", ["A", "B"])
+def test_eri_blocks(jkmod, basis):
+    wl = synth.small_workload(2, basis, seed=21)
+    say("eri blocks", basis, wl.mol.nshell)
+    plan = jkmod.Plan(wl.mol)
+    for q in _class_samples(wl.mol):
+        ref = o.eri_block(wl.mol, *q)
+        got = plan.eri_block(*q)
+        err = np.abs(got - ref).max()
+        assert err <= 1e-12 * max(1.0, np.abs(ref).max()), (q, err)
+        got32 = plan.eri_block(*q, precision="fp32")
+        assert np.abs(got32 - ref).max() <= 2e-5 * max(1e-3, np.abs(ref).max()), q
+
+
+@pytest.mark.parametrize("basis", ["A", "B"])
+def test_schwarz(jkmod, basis):
+    wl = synth.small_workload(3, basis, seed=5)
+    say("schwarz", basis)
+    plan = jkmod.Plan(wl.mol)
+    np.testing.assert_allclose(plan.schwarz(), o.schwarz(wl.mol), rtol=1e-12, atol=1e-300)
+
+
+# ---------------------------------------------------------------------------
+# full J/K at small sizes (several tiles, ragged tails)
+# ---------------------------------------------------------------------------
+def test_jk_c0(jkmod, torch_cuda):
+    wl = synth.workload("c0")
+    say("c0")
+    J0, K0, n0 = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
+    plan, J, K = run_gpu(jkmod, torch_cuda, wl)
+    assert np.abs(J - J0).max() <= TOL
+    assert np.abs(K - K0).max() <= TOL
+    assert abs(plan.stats().nquartets - n0) <= 2
+    # run-to-run spread from atomic ordering
+    _, J2, K2 = run_gpu(jkmod, torch_cuda, wl, plan=plan)
+    assert np.abs(J2 - J).max() <= 1e-13 and np.abs(K2 - K).max() <= 1e-13
+
+
+@pytest.mark.parametrize("basis,nw,nset,cut", [("B", 2, 2, 1e-13), ("A", 5, 1, 1e-10), ("B", 3, 3, 1e-13), ("A", 1, 1, 0.0)])
+def test_jk_small(jkmod, torch_cuda, basis, nw, nset, cut):
+    wl = synth.small_workload(nw, basis, seed=40 + nw, nset=nset)
+    wl.cutoff = cut
+    say("small", basis, nw, nset, cut)
+    J0, K0, n0 = o.jk(wl.mol, wl.D, cut, mode=1)
+    plan, J, K = run_gpu(jkmod, torch_cuda, wl)
+    assert np.abs(J - J0).max() <= TOL
+    assert np.abs(K - K0).max() <= TOL
+
+
+def test_flags_and_accumulate(jkmod, torch_cuda):
+    import torch
+    wl = synth.small_workload(2, "A", seed=3)
+    plan = jkmod.Plan(wl.mol)
+    D = torch.from_numpy(wl.D).cuda()
+    J, K = plan.execute(D)
+    Jo, _ = plan.execute(D, flags=jkmod.JK_DO_J)
+    _, Ko = plan.execute(D, flags=jkmod.JK_DO_K)
+    J2, K2 = J.clone(), K.clone()
+    plan.execute(D, J=J2, K=K2, flags=jkmod.JK_DO_J | jkmod.JK_DO_K | jkmod.JK_ACCUMULATE)
+    torch.cuda.synchronize()
+    assert torch.allclose(Jo, J, atol=1e-14) and torch.allclose(Ko, K, atol=1e-14)
+    assert torch.allclose(J2, 2 * J, atol=1e-13) and torch.allclose(K2, 2 * K, atol=1e-13)
+    with pytest.raises(jkmod.JKError) as e:
+        plan.execute(D, omega=0.3)
+    assert e.value.code == jkmod.JK_EUNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# mixed precision
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("basis", ["A", "B"])
+def test_mixed_small(jkmod, torch_cuda, basis):
+    wl = synth.small_workload(4, basis, seed=77)
+    say("mixed", basis)
+    J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
+    ej0, ek0 = o.energies(wl.D, J0, K0)
+    plan, J, K = run_gpu(jkmod, torch_cuda, wl, precision="mixed")
+    ej, ek = o.energies(wl.D, J, K)
+    assert abs(ej[0] - ej0[0]) <= 1e-6 and abs(ek[0] - ek0[0]) <= 1e-6
+    assert np.abs(J - J0).max() <= 1e-6 and np.abs(K - K0).max() <= 1e-6
+    _, J32, K32 = run_gpu(jkmod, torch_cuda, wl, precision="fp32", plan=plan)
+    assert np.abs(J32 - J0).max() <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads: sampled blocks from the definition + invariants
+# ---------------------------------------------------------------------------
+def _sample_pairs(mol, rng, n):
+    ns = mol.nshell
+    ls = np.asarray(mol.l)
+    hi = np.flatnonzero(ls == ls.max())
+    out = [(int(hi[0]), int(hi[-1])), (int(hi[1]), 0)]
+    while len(out) < n:
+        out.append((int(rng.integers(ns)), int(rng.integers(ns))))
+    return out
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_full_size_sampled(jkmod, torch_cuda, name):
+    wl = synth.workload(name)
+    say("full", name, wl.mol.nshell, wl.mol.nao)
+    plan, J, K = run_gpu(jkmod, torch_cuda, wl)
+    Q = plan.schwarz()
+    rng = np.random.default_rng(1)
+    jp = _sample_pairs(wl.mol, rng, 4)
+    kp = _sample_pairs(wl.mol, rng, 4)
+    say("oracle blocks", name)
+    Jb, Kb = o.jk_blocks(wl.mol, wl.D, Q, jp, kp, wl.cutoff)
+    off = wl.mol.ao_offsets()
+    for (I, Jx), blk in zip(jp, Jb):
+        assert np.abs(J[:, off[I]:off[I + 1], off[Jx]:off[Jx + 1]] - blk).max() <= TOL, (I, Jx)
+    for (I, Kx), blk in zip(kp, Kb):
+        assert np.abs(K[:, off[I]:off[I + 1], off[Kx]:off[Kx + 1]] - blk).max() <= TOL, (I, Kx)
+    D = wl.D[0]
+    assert np.abs(J[0] - J[0].T).max() <= 1e-12
+    assert np.abs(K[0] - K[0].T).max() <= 1e-12
+    tj, tk = float(np.sum(D * J[0])), float(np.sum(D * K[0]))
+    assert tj > 0 and 0 <= tk <= tj
