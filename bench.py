@@ -1,0 +1,175 @@
+#!/usr/bin/env python
+"""J/K build benchmark on one MI355X.
+
+Workload (default): 64 waters on a 4x4x4 lattice, split-valence +
+polarisation Cartesian basis (6-31G*-shaped), 1216 AOs, one density,
+Schwarz cutoff 1e-13.  Inputs are seeded and synthetic and resident in HBM
+before the timed region; a step is one full J+K build (every hot-path
+kernel: density transform when spherical, all class kernels, finalize).
+
+Prints one JSON line: FP64 builds/s as ``value``, ERI quartets/s, the mixed
+FP32/FP64 rate and its energy error against the FP64 GPU build, the
+roofline of the dominant kernel from HIP events over the timed region, and
+the CPU reference timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "J/K builds/s + ERI quartets/s, FP64 vs mixed FP32/FP64 at |dE|<=1e-6 Eh"
+PEAK_FP64_VECTOR = 78.6   # TFLOP/s, MI355X FP64 vector
+PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X FP32 vector
+
+WORKLOAD_TEXT = {
+    "c0": "3 waters, basis A (6-31G*-shaped, Cartesian), 57 AOs, 1 density, cutoff 1e-13",
+    "c1": "64 waters 4x4x4 lattice, basis A (6-31G*-shaped, Cartesian), 1216 AOs, 1 density, cutoff 1e-13",
+    "c2": "32 waters, basis B (TZ2P-shaped, spherical, up to f), 1376 AOs, 1 density, cutoff 1e-13",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(plan, D, J, K, precision, steps, warmup, torch, profile=False):
+    for _ in range(warmup):
+        plan.execute(D, J, K, precision=precision)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(D, J, K, precision=precision)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    tim = plan.timings() if profile else []
+    if profile:
+        plan.profile(False)
+    return dt, tim
+
+
+def cpu_baseline(wl, target_s: float):
+    """Time the oracle's eight-fold build over a random sample of bra shell
+    pairs (all canonical kets of each) and scale to one full build."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    orc.build_oracle(force=False)
+    Q = orc.schwarz(wl.mol)
+    ns = wl.mol.nshell
+    npair = ns * (ns + 1) // 2
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(npair)
+    n = 32
+    used, spent = 0, 0.0
+    while True:
+        sel = order[used:used + n]
+        t0 = time.perf_counter()
+        orc.jk_subset(wl.mol, wl.D, Q, sel, wl.cutoff)
+        spent += time.perf_counter() - t0
+        used += sel.size
+        if spent >= target_s or used >= npair:
+            break
+        # aim the next chunk at the remaining time
+        n = int(min(npair - used, max(32, used * (target_s - spent) / max(spent, 1e-3))))
+    full_s = spent * npair / used
+    return {"value": 1.0 / full_s, "unit": "builds/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"eight-fold oracle over {used} random bra shell pairs of {npair} (each with all its "
+                      f"canonical kets), {spent:.1f} s, scaled by {npair}/{used} to one build "
+                      f"({full_s:.0f} s per build)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--mix-threshold", type=float, default=1e-4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); multi-GPU sharding is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2507_09772_amd import jk, synth
+
+    torch.cuda.set_device(0)
+    wl = synth.workload(args.workload)
+    log(f"workload {args.workload}: {wl.mol.nshell} shells, {wl.mol.nao} AOs")
+    t0 = time.perf_counter()
+    plan = jk.Plan(wl.mol, wl.cutoff)
+    st = plan.stats()
+    log(f"plan: {time.perf_counter() - t0:.2f} s, {st.nquartets} quartets, {st.nprim_quartets} primitive "
+        f"quartets, {st.nclasses} classes")
+    D = torch.from_numpy(wl.D).cuda()
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+
+    dt64, tim64 = timed_steps(plan, D, J, K, "fp64", args.steps, args.warmup, torch, profile=True)
+    log(f"fp64: {dt64 * 1e3:.2f} ms/build")
+    D_h = wl.D
+    J64, K64 = J.cpu().numpy(), K.cpu().numpy()
+    ej64 = 2.0 * float(np.sum(D_h * J64))
+    ek64 = float(np.sum(D_h * K64))
+
+    # dominant kernel: the (class, precision) with most time over the timed region
+    dom = max(tim64, key=lambda t: t.ms)
+    avg_ms = dom.ms / dom.launches
+    achieved = dom.model_flops / (avg_ms * 1e-3) / 1e12
+    kname = f"jk_k{1 if (((dom.li+1)*(dom.li+2)//2)*((dom.lj+1)*(dom.lj+2)//2)*((dom.lk+1)*(dom.lk+2)//2)*((dom.ll+1)*(dom.ll+2)//2)) <= 36 else 2}"
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VECTOR, "traffic": None,
+                "kernel": f"{kname}<{dom.li},{dom.lj},{dom.lk},{dom.ll},double> class ({dom.li}{dom.lj}|{dom.lk}{dom.ll}) "
+                          f"primitive pairs {dom.npb}x{dom.npk}",
+                "avg_launch_ms": avg_ms, "model_flops_per_launch": dom.model_flops,
+                "share_of_build": dom.ms / dom.launches / (dt64 * 1e3)}
+    whole = st.model_flops / dt64 / 1e12
+    top = sorted(tim64, key=lambda t: -t.ms)[:12]
+    for t in top:
+        log(f"  ({t.li}{t.lj}|{t.lk}{t.ll}) np {t.npb}x{t.npk}: {t.ms / t.launches:8.3f} ms  "
+            f"{t.nquartets:11d} q  {t.model_flops / (t.ms / t.launches * 1e-3) / 1e12:6.2f} TF/s")
+
+    out = {"metric": METRIC, "value": 1.0 / dt64, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt64 * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded water lattice, random orthonormal C)",
+           "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "nset": 1,
+                      "precision": "fp64", "cutoff": wl.cutoff},
+           "quartets_per_s": st.nquartets / dt64, "prim_quartets_per_s": st.nprim_quartets / dt64,
+           "nquartets": st.nquartets, "model_tflops": whole, "model_frac_fp64_peak": whole / PEAK_FP64_VECTOR,
+           "E_J": ej64, "E_K": ek64, "roofline": roofline}
+
+    if not args.no_mixed:
+        dtm, timm = timed_steps(plan, D, J, K, "mixed", args.steps, args.warmup, torch, profile=True)
+        Jm, Km = J.cpu().numpy(), K.cpu().numpy()
+        ejm, ekm = 2.0 * float(np.sum(D_h * Jm)), float(np.sum(D_h * Km))
+        f32 = sum(t.ms for t in timm if t.precision == jk.JK_FP32)
+        f64 = sum(t.ms for t in timm if t.precision == jk.JK_FP64)
+        log(f"mixed: {dtm * 1e3:.2f} ms/build (fp64 kernels {f64 / args.steps:.2f} ms, fp32 kernels "
+            f"{f32 / args.steps:.2f} ms), dE_J {ejm - ej64:.2e} dE_K {ekm - ek64:.2e}")
+        out["mixed"] = {"builds_per_s": 1.0 / dtm, "quartets_per_s": st.nquartets / dtm, "ms_per_step": dtm * 1e3,
+                        "speedup_vs_fp64": dt64 / dtm, "dE_J_vs_fp64_gpu": ejm - ej64, "dE_K_vs_fp64_gpu": ekm - ek64,
+                        "max_dJ_vs_fp64_gpu": float(np.abs(Jm - J64).max()),
+                        "max_dK_vs_fp64_gpu": float(np.abs(Km - K64).max()),
+                        "threshold": args.mix_threshold}
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

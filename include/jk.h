@@ -162,6 +162,27 @@ int jk_rys_eval(int32_t n, const double *T_host, int32_t count, int32_t precisio
  * them (table + downward recursion), out [count][m+1].  m <= 1.  Synchronous. */
 int jk_boys_eval(int32_t m, const double *T_host, int32_t count, int32_t precision, double *out_host);
 
+/*
+ * Per-kernel timing (measurement support).  While enabled, jk_execute
+ * records a HIP event on its stream before and after every class-kernel
+ * launch, waits for the last one before returning, and adds each launch's
+ * duration to the class's running total.  jk_plan_profile(plan, 1) resets
+ * the totals; jk_plan_timings copies up to cap entries (one per class and
+ * precision that ran) and stores the number available in *count.
+ */
+typedef struct {
+    int32_t li, lj, lk, ll;     /* angular momenta of the class */
+    int32_t npb, npk;           /* primitive pairs per bra / ket pair */
+    int32_t precision;          /* JK_FP64 or JK_FP32 */
+    int32_t launches;           /* launches summed into ms */
+    int64_t nquartets;          /* significant unique quartets of the class */
+    double model_flops;         /* algorithmic FLOPs of one launch, nset = 1 */
+    double ms;                  /* summed kernel time */
+} jk_class_timing;
+
+int jk_plan_profile(jk_plan *plan, int32_t enable);
+int jk_plan_timings(const jk_plan *plan, jk_class_timing *out, int32_t cap, int32_t *count);
+
 const char *jk_last_error(void);
 
 #ifdef __cplusplus

@@ -636,6 +636,82 @@ int oracle_jk_blocks(BASIS_ARGS, const double *D, int nset, double cutoff, const
     return 0;
 }
 
+/*
+ * Eight-fold digestion restricted to the bra pair indices ij in sel[0..nsel)
+ * (ij = I(I+1)/2 + J, every canonical ket kl <= ij): a bounded sample of the
+ * full build, used only to time the reference on the host.  J', K' are the
+ * unsymmetrised partial accumulators [nset][nao_cart][nao_cart] (Cartesian);
+ * *nsig receives the number of significant quartets processed.
+ */
+int oracle_jk_subset(BASIS_ARGS, const double *D, int nset, double cutoff, const double *Q, int nsel,
+                     const int *sel, double *Jp_out, double *Kp_out, long long *nsig) {
+    obasis b;
+    if (ob_init(&b, BASIS_PASS)) return -1;
+    const int ns_ = b.ns, nc = b.nao_cart, ne = b.nao_ext;
+    double c2s_store[OR_LMAX + 1][OR_MAXNC * (2 * OR_LMAX + 1)];
+    const double *Tl[OR_LMAX + 1];
+    load_c2s(c2s_store, Tl);
+    double *Dc = (double *)malloc(sizeof(double) * nset * nc * nc);
+    for (int s = 0; s < nset; ++s) d_to_cart(&b, D + (size_t)s * ne * ne, Dc + (size_t)s * nc * nc, Tl);
+    memset(Jp_out, 0, sizeof(double) * nset * nc * nc);
+    memset(Kp_out, 0, sizeof(double) * nset * nc * nc);
+    long long count = 0;
+#pragma omp parallel reduction(+ : count)
+    {
+        md_ws w; ws_init(&w);
+        double *blk = (double *)malloc(sizeof(double) * OR_MAXNC * OR_MAXNC * OR_MAXNC * OR_MAXNC);
+        double *Jp = (double *)calloc((size_t)nset * nc * nc, sizeof(double));
+        double *Kp = (double *)calloc((size_t)nset * nc * nc, sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+        for (int si = 0; si < nsel; ++si) {
+            const int ij = sel[si];
+            int I = (int)((sqrt(8.0 * ij + 1.0) - 1.0) / 2.0);
+            while (I * (I + 1) / 2 > ij) --I;
+            while ((I + 1) * (I + 2) / 2 <= ij) ++I;
+            const int J = ij - I * (I + 1) / 2;
+            for (int kl = 0; kl <= ij; ++kl) {
+                int K = (int)((sqrt(8.0 * kl + 1.0) - 1.0) / 2.0);
+                while (K * (K + 1) / 2 > kl) --K;
+                while ((K + 1) * (K + 2) / 2 <= kl) ++K;
+                const int L = kl - K * (K + 1) / 2;
+                if (Q[I * ns_ + J] * Q[K * ns_ + L] < cutoff) continue;
+                ++count;
+                double wgt = 1.0;
+                if (I == J) wgt *= 0.5;
+                if (K == L) wgt *= 0.5;
+                if (ij == kl) wgt *= 0.5;
+                eri_block(&b, I, J, K, L, blk, &w);
+                const int ni = OR_NC(b.l[I]), nj = OR_NC(b.l[J]), nk = OR_NC(b.l[K]), nl = OR_NC(b.l[L]);
+                for (int s = 0; s < nset; ++s) {
+                    const double *d = Dc + (size_t)s * nc * nc;
+                    double *jj = Jp + (size_t)s * nc * nc, *kk = Kp + (size_t)s * nc * nc;
+                    for (int a = 0; a < ni; ++a)
+                        for (int bb = 0; bb < nj; ++bb)
+                            for (int c = 0; c < nk; ++c)
+                                for (int dd = 0; dd < nl; ++dd) {
+                                    const double v = wgt * blk[((a * nj + bb) * nk + c) * nl + dd];
+                                    const int ia = b.coff[I] + a, ib = b.coff[J] + bb, ic = b.coff[K] + c, id = b.coff[L] + dd;
+                                    jj[ia * nc + ib] += 2.0 * v * d[ic * nc + id];
+                                    jj[ic * nc + id] += 2.0 * v * d[ia * nc + ib];
+                                    kk[ia * nc + ic] += v * d[ib * nc + id];
+                                    kk[ia * nc + id] += v * d[ib * nc + ic];
+                                    kk[ib * nc + ic] += v * d[ia * nc + id];
+                                    kk[ib * nc + id] += v * d[ia * nc + ic];
+                                }
+                }
+            }
+        }
+#pragma omp critical
+        {
+            for (size_t x = 0; x < (size_t)nset * nc * nc; ++x) { Jp_out[x] += Jp[x]; Kp_out[x] += Kp[x]; }
+        }
+        free(Jp); free(Kp); free(blk); ws_free(&w);
+    }
+    if (nsig) *nsig = count;
+    free(Dc); ob_free(&b);
+    return 0;
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

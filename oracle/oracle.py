@@ -179,6 +179,27 @@ def jk_blocks(mol, D: np.ndarray, Q: np.ndarray, jpairs, kpairs, cutoff: float =
     return outJ, outK
 
 
+def jk_subset(mol, D: np.ndarray, Q: np.ndarray, sel, cutoff: float = 1e-13):
+    """Eight-fold digestion over the bra pair indices in ``sel`` only
+    (unsymmetrised Cartesian partial J', K').  Returns (J', K', nsig)."""
+    b = _Basis(mol)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    if D.ndim == 2:
+        D = D[None]
+    nset = D.shape[0]
+    nc = int(sum((int(x) + 1) * (int(x) + 2) // 2 for x in mol.l))
+    Jp = np.zeros((nset, nc, nc))
+    Kp = np.zeros((nset, nc, nc))
+    s = np.ascontiguousarray(sel, dtype=np.int32)
+    Qc = np.ascontiguousarray(Q, dtype=np.float64)
+    cnt = ctypes.c_longlong()
+    rc = _load().oracle_jk_subset(*b.args(), _dp(D), ctypes.c_int(nset), ctypes.c_double(cutoff), _dp(Qc),
+                                  ctypes.c_int(s.size), _ip(s), _dp(Jp), _dp(Kp), ctypes.byref(cnt))
+    if rc:
+        raise ValueError("invalid basis")
+    return Jp, Kp, int(cnt.value)
+
+
 def c2s(l: int) -> np.ndarray:
     """[(2l+1), ncart] real-solid-harmonic coefficients (rows m = -l..l;
     l = 1 stays x, y, z)."""

@@ -277,6 +277,10 @@ struct jk_plan {
     Tables tab{};
     jk_stats stats{};
     int device = 0;
+    // per-kernel timing
+    bool profile = false;
+    std::vector<hipEvent_t> events;
+    std::vector<jk_class_timing> timing;  // [2 * class + (FP32 ? 1 : 0)]
 
     template <typename T>
     int alloc(T **p, size_t n) {
@@ -294,6 +298,7 @@ struct jk_plan {
         return 0;
     }
     ~jk_plan() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }
 };
@@ -660,7 +665,22 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     a.nshell = P->ns;
     a.mix_thr = mix_threshold;
     a.tab = P->tab;
-    for (const ClassTask &c : P->cls) {
+    // launches in order: (class, precision) -> timing slot
+    std::vector<int> slots;
+    int nev = 0;
+    auto mark = [&](int slot) -> int {
+        if (!P->profile) return 0;
+        if ((int)P->events.size() <= nev) {
+            hipEvent_t ev;
+            HIPCHK(hipEventCreate(&ev));
+            P->events.push_back(ev);
+        }
+        HIPCHK(hipEventRecord(P->events[nev++], s));
+        if (slot >= 0) slots.push_back(slot);
+        return 0;
+    };
+    for (size_t ci = 0; ci < P->cls.size(); ++ci) {
+        const ClassTask &c = P->cls[ci];
         const ClassEntry &e = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
         a.bra_list = c.d_bra;
         a.ket_list = c.d_ket;
@@ -673,11 +693,24 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
         a.npk = c.npk;
         if (precision == JK_FP64 || precision == JK_MIXED) {
             a.sel = precision == JK_MIXED ? SEL_HIGH : SEL_ALL;
+            if ((rc = mark((int)(2 * ci)))) return rc;
             HIPCHK(e.jk64(a, s));
         }
         if (precision == JK_FP32 || precision == JK_MIXED) {
             a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
+            if ((rc = mark((int)(2 * ci + 1)))) return rc;
             HIPCHK(e.jk32(a, s));
+        }
+    }
+    if (P->profile) {
+        if ((rc = mark(-1))) return rc;
+        HIPCHK(hipEventSynchronize(P->events[nev - 1]));
+        for (size_t k = 0; k < slots.size(); ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, P->events[k], P->events[k + 1]));
+            jk_class_timing &t = P->timing[slots[k]];
+            t.ms += ms;
+            t.launches += 1;
         }
     }
     const int acc = (flags & JK_ACCUMULATE) ? 1 : 0;
@@ -686,6 +719,35 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Kc, K, P->nao, P->naoc, nset, P->sph, acc);
     HIPCHK(hipGetLastError());
     return JK_OK;
+}
+
+extern "C" int jk_plan_profile(jk_plan *P, int32_t enable) {
+    if (!P) return fail(JK_EINVAL, "plan is NULL");
+    P->profile = enable != 0;
+    P->timing.assign(2 * P->cls.size(), jk_class_timing{});
+    for (size_t ci = 0; ci < P->cls.size(); ++ci)
+        for (int k = 0; k < 2; ++k) {
+            const ClassTask &c = P->cls[ci];
+            jk_class_timing &t = P->timing[2 * ci + k];
+            t.li = c.li; t.lj = c.lj; t.lk = c.lk; t.ll = c.ll;
+            t.npb = c.npb; t.npk = c.npk;
+            t.precision = k ? JK_FP32 : JK_FP64;
+            t.nquartets = c.nq;
+            t.model_flops = c.flops;
+        }
+    return 0;
+}
+
+extern "C" int jk_plan_timings(const jk_plan *P, jk_class_timing *out, int32_t cap, int32_t *count) {
+    if (!P || !count || (cap > 0 && !out)) return fail(JK_EINVAL, "NULL argument");
+    int n = 0;
+    for (const jk_class_timing &t : P->timing) {
+        if (t.launches == 0) continue;
+        if (n < cap) out[n] = t;
+        ++n;
+    }
+    *count = n;
+    return 0;
 }
 
 extern "C" int jk_build(const jk_basis *basis, const double *D, int32_t nset, double cutoff, int32_t precision, double *J, double *K,

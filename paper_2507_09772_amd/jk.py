@@ -38,6 +38,13 @@ class Stats(ctypes.Structure):
                 ("npairs", ctypes.c_int32), ("setup_ms", ctypes.c_double), ("model_flops", ctypes.c_double)]
 
 
+class ClassTiming(ctypes.Structure):
+    _fields_ = [("li", ctypes.c_int32), ("lj", ctypes.c_int32), ("lk", ctypes.c_int32), ("ll", ctypes.c_int32),
+                ("npb", ctypes.c_int32), ("npk", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("launches", ctypes.c_int32), ("nquartets", ctypes.c_int64), ("model_flops", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -63,6 +70,8 @@ def lib():
         L.jk_batch_execute.argtypes = [vp, vp, vp, vp, vp]
         L.jk_batch_destroy.argtypes = [vp]
         L.jk_batch_destroy.restype = None
+        L.jk_plan_profile.argtypes = [vp, i32]
+        L.jk_plan_timings.argtypes = [vp, ctypes.POINTER(ClassTiming), i32, ctypes.POINTER(i32)]
         L.jk_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -157,6 +166,17 @@ class Plan:
         if squeeze:
             return (J[0] if J is not None else None), (K[0] if K is not None else None)
         return J, K
+
+    def profile(self, enable: bool = True):
+        """Per-kernel HIP-event timing of later executes (resets totals)."""
+        _check(lib().jk_plan_profile(self.h, int(enable)))
+
+    def timings(self) -> list:
+        n = ctypes.c_int32()
+        _check(lib().jk_plan_timings(self.h, None, 0, ctypes.byref(n)))
+        arr = (ClassTiming * max(1, n.value))()
+        _check(lib().jk_plan_timings(self.h, arr, n.value, ctypes.byref(n)))
+        return [arr[i] for i in range(n.value)]
 
     def eri_block(self, I, J, K, L, precision="fp64") -> np.ndarray:
         n = [(int(self._b.l[x]) + 1) * (int(self._b.l[x]) + 2) // 2 for x in (I, J, K, L)]

@@ -1,0 +1,45 @@
+"""Write reference values for the full-size workloads with the CPU oracle.
+
+Calls only oracle/ (and the seeded input generator).  For each workload it
+stores E_J = 2 Tr(D J) and E_K = Tr(D K) (closed-shell reading, see DESIGN),
+the number of significant unique quartets, and every 97th element of J and
+K in row-major order.  Run: python tests/golden/make_golden.py c1 c2
+(about half an hour per workload on 8 cores).
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import oracle as o  # noqa: E402
+from paper_2507_09772_amd import synth  # noqa: E402
+
+STRIDE = 97
+
+
+def main(names):
+    o.build_oracle(force=False)
+    for name in names:
+        wl = synth.workload(name)
+        t0 = time.time()
+        Q = o.schwarz(wl.mol)
+        J, K, nsig = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, Q=Q)
+        dt = time.time() - t0
+        ej, ek = o.energies(wl.D, J, K)
+        out = dict(workload=name, nao=int(wl.mol.nao), cutoff=wl.cutoff, nsig=nsig,
+                   E_J=float(ej[0]), E_K=float(ek[0]), stride=STRIDE,
+                   J=J.ravel()[::STRIDE].tolist(), K=K.ravel()[::STRIDE].tolist(),
+                   oracle_seconds=dt, oracle_threads=o.num_threads())
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_jk.json")
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print(name, "E_J", ej[0], "E_K", ek[0], "nsig", nsig, f"{dt:.0f}s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["c1", "c2"])
