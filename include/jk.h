@@ -183,6 +183,24 @@ typedef struct {
 int jk_plan_profile(jk_plan *plan, int32_t enable);
 int jk_plan_timings(const jk_plan *plan, jk_class_timing *out, int32_t cap, int32_t *count);
 
+/*
+ * Kernel tuning table (the per-device heuristics database of Section 3).
+ * Every canonical angular class (li >= lj, lk >= ll, (lk,ll) <= (li,lj))
+ * has up to two kernel families: 1 = one lane per quartet with the integral
+ * block in registers, 2 = a lane group per quartet with 2-D integrals in
+ * LDS.  jk_tune_set picks the family for one class and precision (JK_FP64
+ * or JK_FP32; family 0 restores the built-in default); plans read the table
+ * when they are created.  At load time the library reads tune_gfx950.txt
+ * next to itself (or the file named by JK_TUNE_DB): one
+ * "li lj lk ll precision family" line per entry, '#' comments.
+ * jk_tune_get reports the family a new plan would use and a bit mask of
+ * the built families (1: family 1, 2: family 2).
+ */
+int jk_tune_set(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family);
+int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t *family,
+                int32_t *available);
+int jk_tune_load(const char *path);
+
 const char *jk_last_error(void);
 
 #ifdef __cplusplus

@@ -18,11 +18,18 @@
 #include "jk_registry.h"
 #include "tables/jk_tables.h"
 
+#include <dlfcn.h>
+
 namespace jk {
 ClassEntry g_classes[NCLS];
 }
 
 using namespace jk;
+
+// Tuning table: kernel family per (class, precision); 0 = built-in default.
+// Loaded from the shipped per-device file at library load, settable through
+// jk_tune_set, read by jk_plan_create.
+static int32_t g_tune[NCLS][2];
 
 // ---------------------------------------------------------------------------
 // errors
@@ -134,6 +141,10 @@ __global__ void k_schwarz(const double *blocks, int nab, const int32_t *pair_ids
     double m = 0.0;
     for (int e = 0; e < nab; ++e) m = fmax(m, fabs(b[e * nab + e]));
     pairs[pair_ids[t]].q = sqrt(m);
+}
+
+__global__ void k_fill_i32(int32_t *p, int n) {
+    for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
 }
 
 __global__ void k_fill(double *p, int64_t n, double v) {
@@ -251,10 +262,12 @@ struct DevBuf {
 
 struct ClassTask {
     int li, lj, lk, ll;
-    int bt, kt, same, npb, npk, nbra, ntiles;
-    int64_t nq, npq;
+    int bt, kt, same, npb, npk, nbra;
+    int fam[2];          // family per precision (0 FP64, 1 FP32)
+    int ntiles[2];       // per family - 1
+    int64_t nq, npq, list_off;
     double flops;
-    int32_t *d_bra = nullptr, *d_cnt = nullptr, *d_tile = nullptr;
+    int32_t *d_bra = nullptr, *d_cnt = nullptr, *d_tile[2] = {nullptr, nullptr};
     const int32_t *d_ket = nullptr;
 };
 
@@ -273,6 +286,8 @@ struct jk_plan {
     AoMaps maps{};
     double *d_Jc = nullptr, *d_Kc = nullptr, *d_Dc = nullptr;
     int scratch_nset = 0, dc_nset = 0;
+    int32_t *d_list = nullptr, *d_list_cnt = nullptr;  // mixed split
+    bool last_mixed = false;
     float *d_dmax = nullptr;
     Tables tab{};
     jk_stats stats{};
@@ -506,10 +521,18 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
             c.bt = bt; c.kt = kt; c.same = bt == kt;
             c.npb = P->hpairs[ptype_first[bt]].npp;
             c.npk = P->hpairs[ptype_first[kt]].npp;
-            const int qpt = quartets_per_tile(c.li, c.lj, c.lk, c.ll);
-            std::vector<int32_t> bl, cn, to;
+            const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
+            const bool avail[2] = {ce.tiles[0][0] != nullptr, ce.tiles[1][0] != nullptr};
+            if (!avail[0] && !avail[1]) return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) not built", c.li, c.lj, c.lk, c.ll);
+            for (int pr = 0; pr < 2; ++pr) {
+                int f = g_tune[class_id(c.li, c.lj, c.lk, c.ll)][pr];
+                if (f < 1 || f > 2 || !avail[f - 1]) f = default_family(c.li, c.lj, c.lk, c.ll);
+                if (!avail[f - 1]) f = 3 - f;
+                c.fam[pr] = f;
+            }
+            std::vector<int32_t> bl, cn, to[2];
             const auto &kq = sortedq[kt];
-            int64_t tiles = 0;
+            int64_t tiles[2] = {0, 0};
             for (size_t i = 0; i < sorted[bt].size(); ++i) {
                 const double qb = sortedq[bt][i];
                 // kets j with qb * kq[j] >= cutoff form a prefix
@@ -524,20 +547,26 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 if (cnt == 0) continue;
                 bl.push_back(sorted[bt][i]);
                 cn.push_back((int32_t)cnt);
-                to.push_back((int32_t)tiles);
-                tiles += (cnt + qpt - 1) / qpt;
+                for (int f = 0; f < 2; ++f) {
+                    to[f].push_back((int32_t)tiles[f]);
+                    const int qpt = quartets_per_tile(f + 1, c.li, c.lj, c.lk, c.ll);
+                    tiles[f] += (cnt + qpt - 1) / qpt;
+                }
                 c.nq += cnt;
             }
             if (c.nq == 0) continue;
-            if (tiles > INT32_MAX) return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has too many tiles", c.li, c.lj, c.lk, c.ll);
+            if (tiles[0] > INT32_MAX || tiles[1] > INT32_MAX || c.nq > INT32_MAX)
+                return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has too many quartets", c.li, c.lj, c.lk, c.ll);
             c.nbra = (int)bl.size();
-            c.ntiles = (int)tiles;
             c.npq = c.nq * c.npb * c.npk;
             c.flops = (double)c.npq * flops_prim(c.li, c.lj, c.lk, c.ll) + (double)c.nq * flops_digest(c.li, c.lj, c.lk, c.ll);
-            if ((rc = P->put(&c.d_bra, bl)) || (rc = P->put(&c.d_cnt, cn)) || (rc = P->put(&c.d_tile, to))) return rc;
+            if ((rc = P->put(&c.d_bra, bl)) || (rc = P->put(&c.d_cnt, cn))) return rc;
+            for (int f = 0; f < 2; ++f) {
+                c.ntiles[f] = (int)tiles[f];
+                if (avail[f] && (rc = P->put(&c.d_tile[f], to[f]))) return rc;
+            }
             c.d_ket = d_sorted[kt];
-            if (!g_classes[class_id(c.li, c.lj, c.lk, c.ll)].jk64)
-                return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) not built", c.li, c.lj, c.lk, c.ll);
+            c.list_off = nq_tot;
             nq_tot += c.nq;
             npq_tot += c.npq;
             flops_tot += c.flops;
@@ -583,7 +612,86 @@ extern "C" int jk_plan_info(const jk_plan *P, int32_t *nao, int32_t *nao_cart) {
 extern "C" int jk_plan_stats(const jk_plan *P, jk_stats *st) {
     if (!P || !st) return fail(JK_EINVAL, "NULL argument");
     *st = P->stats;
+    st->nquartets_fp32 = 0;
+    if (P->last_mixed && P->d_list_cnt && !P->cls.empty()) {
+        std::vector<int32_t> cnt(P->cls.size());
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(cnt.data(), P->d_list_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost));
+        int64_t n64 = 0;
+        for (int32_t v : cnt) n64 += v;
+        st->nquartets_fp32 = P->stats.nquartets - n64;
+    }
     return 0;
+}
+
+// ---------------------------------------------------------------------------
+// tuning table
+// ---------------------------------------------------------------------------
+static bool valid_class(int li, int lj, int lk, int ll) {
+    return li >= lj && lk >= ll && li <= LMAX_BUILT && lk <= LMAX_BUILT && lj >= 0 && ll >= 0 &&
+           (lk < li || (lk == li && ll <= lj));
+}
+
+extern "C" int jk_tune_set(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family) {
+    if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
+    if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
+    if (family < 0 || family > 2) return fail(JK_EINVAL, "family must be 0, 1 or 2");
+    const ClassEntry &e = g_classes[class_id(li, lj, lk, ll)];
+    if (family && !e.tiles[family - 1][0]) return fail(JK_EUNSUPPORTED, "family %d is not built for (%d%d|%d%d)", family, li, lj, lk, ll);
+    g_tune[class_id(li, lj, lk, ll)][precision == JK_FP32 ? 1 : 0] = family;
+    return 0;
+}
+
+extern "C" int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t *family,
+                           int32_t *available) {
+    if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
+    if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
+    const ClassEntry &e = g_classes[class_id(li, lj, lk, ll)];
+    const int f = g_tune[class_id(li, lj, lk, ll)][precision == JK_FP32 ? 1 : 0];
+    if (family) *family = f ? f : default_family(li, lj, lk, ll);
+    if (available) *available = (e.tiles[0][0] ? 1 : 0) | (e.tiles[1][0] ? 2 : 0);
+    return 0;
+}
+
+extern "C" int jk_tune_load(const char *path) {
+    if (!path) return fail(JK_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(JK_EINVAL, "cannot open %s", path);
+    char line[256];
+    int n = 0, lineno = 0;
+    while (fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int li, lj, lk, ll, pr, fam;
+        if (sscanf(line, "%d %d %d %d %d %d", &li, &lj, &lk, &ll, &pr, &fam) != 6) {
+            fclose(f);
+            return fail(JK_EINVAL, "%s:%d: expected 'li lj lk ll precision family'", path, lineno);
+        }
+        const int rc = jk_tune_set(li, lj, lk, ll, pr, fam);
+        if (rc) { fclose(f); return rc; }
+        ++n;
+    }
+    fclose(f);
+    return 0;
+}
+
+// The shipped table for this device sits next to the library.
+__attribute__((constructor)) static void load_default_tuning() {
+    const char *env = getenv("JK_TUNE_DB");
+    std::string path;
+    if (env && *env) {
+        path = env;
+    } else {
+        Dl_info info;
+        if (!dladdr((void *)&load_default_tuning, &info) || !info.dli_fname) return;
+        path = info.dli_fname;
+        const size_t sl = path.rfind('/');
+        path = (sl == std::string::npos ? std::string(".") : path.substr(0, sl)) + "/tune_gfx950.txt";
+    }
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return;
+    fclose(f);
+    (void)jk_tune_load(path.c_str());
 }
 
 extern "C" int jk_plan_schwarz(const jk_plan *P, double *Q) {
@@ -665,6 +773,16 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     a.nshell = P->ns;
     a.mix_thr = mix_threshold;
     a.tab = P->tab;
+    if (precision == JK_MIXED) {
+        if (!P->d_list) {
+            if ((rc = P->alloc(&P->d_list, (size_t)2 * std::max<int64_t>(P->stats.nquartets, 1))) ||
+                (rc = P->alloc(&P->d_list_cnt, std::max<size_t>(P->cls.size(), 1))))
+                return rc;
+        }
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, P->d_list_cnt, (int)P->cls.size());
+        HIPCHK(hipGetLastError());
+    }
+    P->last_mixed = precision == JK_MIXED;
     // launches in order: (class, precision) -> timing slot
     std::vector<int> slots;
     int nev = 0;
@@ -685,21 +803,34 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
         a.bra_list = c.d_bra;
         a.ket_list = c.d_ket;
         a.bra_cnt = c.d_cnt;
-        a.tile_off = c.d_tile;
         a.nbra = c.nbra;
-        a.ntiles = c.ntiles;
         a.same = c.same;
         a.npb = c.npb;
         a.npk = c.npk;
-        if (precision == JK_FP64 || precision == JK_MIXED) {
-            a.sel = precision == JK_MIXED ? SEL_HIGH : SEL_ALL;
+        if (precision == JK_FP64) {
+            const int f = c.fam[0];
+            a.tile_off = c.d_tile[f - 1];
+            a.ntiles = c.ntiles[f - 1];
+            a.sel = SEL_ALL;
             if ((rc = mark((int)(2 * ci)))) return rc;
-            HIPCHK(e.jk64(a, s));
-        }
-        if (precision == JK_FP32 || precision == JK_MIXED) {
+            HIPCHK(e.tiles[f - 1][0](a, s));
+        } else {
+            // FP32 tile pass (in the mixed split it diverts large-bound
+            // quartets to the list), then the FP64 list pass
+            const int f = c.fam[1];
+            a.tile_off = c.d_tile[f - 1];
+            a.ntiles = c.ntiles[f - 1];
             a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
+            a.list = P->d_list + 2 * c.list_off;
+            a.list_count = P->d_list_cnt + ci;
+            a.nq = (int32_t)c.nq;
             if ((rc = mark((int)(2 * ci + 1)))) return rc;
-            HIPCHK(e.jk32(a, s));
+            HIPCHK(e.tiles[f - 1][1](a, s));
+            if (precision == JK_MIXED) {
+                const int f64 = c.fam[0];
+                if ((rc = mark((int)(2 * ci)))) return rc;
+                HIPCHK(e.list64[f64 - 1](a, s));
+            }
         }
     }
     if (P->profile) {

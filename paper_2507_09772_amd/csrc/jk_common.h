@@ -50,24 +50,31 @@ struct PrimPair {
     double PA[3];   // P - A
 };
 
-// Kernel family per angular class.
+// Kernel families per angular class (both are built where both fit; the
+// planner picks one per class and precision from the tuning table):
 //   1: one lane per quartet (register-resident integral block);
 //   2: a lane group per quartet, 2-D integrals staged in LDS.
-JK_HD constexpr int family(int li, int lj, int lk, int ll) {
-    return ncart(li) * ncart(lj) * ncart(lk) * ncart(ll) <= 36 ? 1 : 2;
-}
+JK_HD constexpr int ncart4(int li, int lj, int lk, int ll) { return ncart(li) * ncart(lj) * ncart(lk) * ncart(ll); }
+JK_HD constexpr bool has_family1(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) <= 81; }
+JK_HD constexpr bool has_family2(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) >= 18; }
+JK_HD constexpr int default_family(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) <= 36 ? 1 : 2; }
 // Family 2: lanes per quartet = ncart(li) * ncart(lk) (slot = (a, c)).
 JK_HD constexpr int k2_slots(int li, int lj, int lk, int ll) { return ncart(li) * ncart(lk); }
 JK_HD constexpr int k2_qw(int li, int lj, int lk, int ll) {
     return k2_slots(li, lj, lk, ll) >= 64 ? 1 : 64 / k2_slots(li, lj, lk, ll);
 }
-// Quartets per wave-tile.
-JK_HD constexpr int quartets_per_tile(int li, int lj, int lk, int ll) {
-    return family(li, lj, lk, ll) == 1 ? 64 : k2_qw(li, lj, lk, ll);
+// Quartets per wave-tile of a family.
+JK_HD constexpr int quartets_per_tile(int fam, int li, int lj, int lk, int ll) {
+    return fam == 1 ? 64 : k2_qw(li, lj, lk, ll);
 }
 
-enum { MODE_JK = 0, MODE_EXPORT = 1 };
-enum { SEL_ALL = 0, SEL_HIGH = 1, SEL_LOW = 2 };
+// Quartet sources: tiles of (bra, Q-sorted ket prefix), an explicit list
+// with digestion (the FP64 part of the mixed split), or an explicit list
+// whose blocks are written out (Schwarz diagonal, test hook).
+enum { MODE_JK = 0, MODE_EXPORT = 1, MODE_LIST = 2 };
+// SEL_LOW: FP32 tile pass of the mixed split; quartets whose bound reaches
+// the threshold are appended to the list for the FP64 list pass instead.
+enum { SEL_ALL = 0, SEL_LOW = 1 };
 
 struct Tables {
     const double *rys;     // degree-major Rys fits, FP64
@@ -88,6 +95,10 @@ struct JkArgs {
     const int32_t *q_bra, *q_ket;
     int32_t nq;
     double *out;
+    // mixed split: appended (bra, ket) pair ids and their count; LIST mode
+    // reads them back (nq is the capacity)
+    int32_t *list;
+    int32_t *list_count;
     // densities and results (Cartesian, [nset][nao][nao])
     const double *D;
     double *J, *K;

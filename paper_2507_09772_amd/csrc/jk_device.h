@@ -36,9 +36,28 @@ namespace jk {
 constexpr double TWO_PI_2_5 = 34.986836655249725;  // 2 pi^(5/2)
 constexpr double SQRT_PI_HALF = 0.88622692545275801;  // sqrt(pi) / 2
 
+// Reciprocal and reciprocal square root: hardware estimate refined by two
+// Newton steps in FP64 (each step doubles the correct bits), hardware
+// instruction alone in FP32.  Arguments are positive and finite here.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+__device__ __forceinline__ double rsq64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
 template <typename R> __device__ __forceinline__ R rsqrt_(R x);
-template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return 1.0 / sqrt(x); }
-template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __frsqrt_rn(x); }
+template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return rsq64(x); }
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <typename R> __device__ __forceinline__ R rcp_(R x);
+template <> __device__ __forceinline__ double rcp_<double>(double x) { return rcp64(x); }
+template <> __device__ __forceinline__ float rcp_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 template <typename R> struct TabSel;
 template <> struct TabSel<double> {
@@ -55,8 +74,11 @@ template <> struct TabSel<float> {
 };
 
 // ---------------------------------------------------------------------------
-// One-root case: Boys function by Taylor expansion of the tabulated F_1 and
-// downward recursion F_0 = 2T F_1 + exp(-T); u = F_1 / F_0, w = F_0.
+// One-root case: u = F_1 / F_0, w = F_0 from the tabulated Boys function.
+// Below the table end both come from the Taylor expansion about the nearest
+// grid point T_j (spacing 1/32), F_m(T) = sum_k F_(m+k)(T_j) (T_j - T)^k / k!,
+// 7 terms in FP64 and 4 in FP32 (no exponential needed).  Above it, the
+// large-T limits F_0 = sqrt(pi/T) / 2 and F_1 = F_0 / (2T).
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u, R &w) {
@@ -66,19 +88,18 @@ __device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u,
         const R *row = boys + j * (JKT_BOYS_MMAX + 1);
         constexpr int NT = sizeof(R) == 8 ? 7 : 4;  // Taylor terms
         R f1 = row[NT];
+        R f0 = row[NT - 1];
 #pragma unroll
-        for (int k = NT - 1; k >= 1; --k) f1 = row[k] + f1 * d * (R)(1.0 / k);
-        const R tt = (R)T;
-        R e;
-        if constexpr (sizeof(R) == 8) e = exp(-T);
-        else e = __expf(-tt);
-        const R f0 = (R)2 * tt * f1 + e;
+        for (int k = NT - 1; k >= 1; --k) {
+            f1 = row[k] + f1 * d * (R)(1.0 / k);
+            f0 = row[k - 1] + f0 * d * (R)(1.0 / k);
+        }
         w = f0;
-        u = f1 / f0;
+        u = f1 * rcp_<R>(f0);
     } else {
         const R rt = rsqrt_<R>((R)T);
         w = (R)SQRT_PI_HALF * rt;
-        u = (R)0.5 / (R)T;
+        u = (R)0.5 * rt * rt;
     }
 }
 
@@ -112,8 +133,8 @@ __device__ __forceinline__ void rys_roots(double T, const Tables &tab, R (&u)[N]
                 w[i] = acc[N + i];
             }
         } else {
-            const R rT = (R)(1.0 / T);
             const R rt = rsqrt_<R>((R)T);
+            const R rT = rt * rt;
             const R *hx = TabSel<R>::hx2(tab) + jkt_herm_offset[N];
             const R *hw = TabSel<R>::hw(tab) + jkt_herm_offset[N];
 #pragma unroll
@@ -146,8 +167,9 @@ __device__ __forceinline__ void rys_root1(double T, int r, const Tables &tab, R 
             u = au;
             w = aw;
         } else {
-            u = TabSel<R>::hx2(tab)[jkt_herm_offset[N] + r] * (R)(1.0 / T);
-            w = TabSel<R>::hw(tab)[jkt_herm_offset[N] + r] * rsqrt_<R>((R)T);
+            const R rt = rsqrt_<R>((R)T);
+            u = TabSel<R>::hx2(tab)[jkt_herm_offset[N] + r] * rt * rt;
+            w = TabSel<R>::hw(tab)[jkt_herm_offset[N] + r] * rt;
         }
     }
 }
@@ -254,10 +276,36 @@ __device__ __forceinline__ float dmax6(const JkArgs &a, const PairRec &B, const 
     return m;
 }
 
-__device__ __forceinline__ bool selected(const JkArgs &a, const PairRec &B, const PairRec &K) {
-    if (a.sel == SEL_ALL) return true;
-    const double bound = B.q * K.q * (double)dmax6(a, B, K);
-    return a.sel == SEL_HIGH ? bound >= a.mix_thr : bound < a.mix_thr;
+// Mixed split, FP32 tile pass: a quartet whose bound Q_IJ Q_KL max|D_block|
+// reaches the threshold is appended (bra, ket) to the FP64 list instead.
+// push: lanes that own an append (one per quartet).  Wave-compacted: one
+// counter atomic per wave.
+__device__ __forceinline__ void list_append(const JkArgs &a, bool push, int bra, int ket) {
+    const unsigned long long m = __ballot(push);
+    if (m == 0ull) return;
+    const int lane = __lane_id();
+    int base = 0;
+    if (lane == 0) base = atomicAdd(a.list_count, (int)__popcll(m));
+    base = __shfl(base, 0, 64);
+    if (push) {
+        const int idx = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+        if (idx < a.nq) {
+            a.list[2 * idx] = bra;
+            a.list[2 * idx + 1] = ket;
+        }
+    }
+}
+
+__device__ __forceinline__ bool above_threshold(const JkArgs &a, const PairRec &B, const PairRec &K) {
+    return B.q * K.q * (double)dmax6(a, B, K) >= a.mix_thr;
+}
+
+__device__ __forceinline__ double pair_weight(int bra, int ket, const PairRec &B, const PairRec &K) {
+    double w = 1.0;
+    if (B.ish == B.jsh) w *= 0.5;
+    if (K.ish == K.jsh) w *= 0.5;
+    if (bra == ket) w *= 0.5;
+    return w;
 }
 
 // Geometry of one primitive quartet.  Differences of centres are formed in
@@ -273,7 +321,8 @@ template <typename R>
 __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const PrimPair &pk) {
     PQuart<R> g;
     const double p = pb.p, q = pk.p;
-    const double rpq = 1.0 / (p + q);
+    const double rs = rsq64(p + q);
+    const double rpq = rs * rs;
     double pq2 = 0.0, d[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
@@ -284,7 +333,7 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
     g.rpq = (R)rpq;
     g.fq = (R)(q * rpq);
     g.fp = (R)(p * rpq);
-    g.pref = (R)(TWO_PI_2_5 * pb.kp * pk.kp * sqrt(rpq));
+    g.pref = (R)(TWO_PI_2_5 * pb.kp * pk.kp * rs);
     g.hb = (R)pb.h;
     g.hk = (R)pk.h;
 #pragma unroll
@@ -298,52 +347,30 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
 
 // ===========================================================================
 // Family 1: one lane per quartet.  The contracted Cartesian block V lives in
-// registers; digestion reduces J_IJ across the wave (the bra is uniform in a
-// tile) and sends the other five blocks straight to FP64 atomics.
+// registers; digestion reduces J_IJ across the wave when the bra is uniform
+// (tiles) and sends the other blocks straight to FP64 atomics.
 // ===========================================================================
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
-__global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
+__device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool valid, double wq, int64_t gout) {
     using C = Cls<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NAB = C::NAB, NCD = C::NCD, NR = C::NR;
-    const int lane = threadIdx.x & 63;
-    int bra, ket;
-    bool valid;
-    double wq = 1.0;
-    if constexpr (MODE == MODE_JK) {
-        const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-        if (wave >= a.ntiles) return;
-        const int i = tile_bra(a.tile_off, a.nbra, wave);
-        const int j = (wave - a.tile_off[i]) * 64 + lane;
-        const int cnt = a.bra_cnt[i];
-        valid = j < cnt;
-        bra = a.bra_list[i];
-        ket = a.ket_list[valid ? j : cnt - 1];
-        if (a.same && j == i) wq *= 0.5;
-    } else {
-        const int g = blockIdx.x * 256 + threadIdx.x;
-        valid = g < a.nq;
-        const int gg = valid ? g : a.nq - 1;
-        bra = a.q_bra[gg];
-        ket = a.q_ket[gg];
-    }
+    constexpr bool BRA_UNIFORM = MODE == MODE_JK;
+    const int lane = __lane_id();
     const PairRec B = a.pairs[bra];
     const PairRec Kt = a.pairs[ket];
-    if constexpr (MODE == MODE_JK) {
-        if (B.ish == B.jsh) wq *= 0.5;
-        if (Kt.ish == Kt.jsh) wq *= 0.5;
-        valid = valid && selected(a, B, Kt);
-    }
     R V[NAB * NCD];
 #pragma unroll
     for (int e = 0; e < NAB * NCD; ++e) V[e] = (R)0;
-    const int npb = MODE == MODE_JK ? a.npb : B.npp;
+    const int npb = BRA_UNIFORM ? a.npb : B.npp;
     const int npk = MODE == MODE_JK ? a.npk : Kt.npp;
     const R ab[3] = {(R)B.ab[0], (R)B.ab[1], (R)B.ab[2]};
     const R cd[3] = {(R)Kt.ab[0], (R)Kt.ab[1], (R)Kt.ab[2]};
-    for (int ib = 0; ib < npb; ++ib) {
-        const PrimPair pb = a.pp[B.pp_off + ib];
-        for (int ik = 0; ik < npk; ++ik) {
-            const PrimPair pk = a.pp[Kt.pp_off + ik];
+    // ket primitive outer (one vector load each), bra primitive inner (the
+    // bra is uniform across a tile, so its records come through scalar loads)
+    for (int ik = 0; ik < npk; ++ik) {
+        const PrimPair pk = a.pp[Kt.pp_off + ik];
+        for (int ib = 0; ib < npb; ++ib) {
+            const PrimPair pb = a.pp[B.pp_off + ib];
             const PQuart<R> g = prim_quartet<R>(pb, pk);
             R u[NR], w[NR];
             rys_roots<NR, R>(g.T, a.tab, u, w);
@@ -381,8 +408,7 @@ __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
     }
     if constexpr (MODE == MODE_EXPORT) {
         if (valid) {
-            const int g = blockIdx.x * 256 + threadIdx.x;
-            double *o = a.out + (int64_t)g * (NAB * NCD);
+            double *o = a.out + gout * (NAB * NCD);
 #pragma unroll
             for (int e = 0; e < NAB * NCD; ++e) o[e] = (double)V[e];
         }
@@ -404,17 +430,27 @@ __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
 #pragma unroll
                     for (int l = 0; l < NL; ++l) dkl[k * NL + l] = D[(Kt.aoi + k) * n + Kt.aoj + l];
                 const double w2 = valid ? 2.0 * wq : 0.0;
-                // J_IJ: reduce over the wave's kets
-                double mine = 0.0;
+                if constexpr (BRA_UNIFORM) {
+                    // J_IJ: reduce over the wave's kets
+                    double mine = 0.0;
 #pragma unroll
-                for (int ab2 = 0; ab2 < NAB; ++ab2) {
-                    double s2 = 0.0;
+                    for (int ab2 = 0; ab2 < NAB; ++ab2) {
+                        double s2 = 0.0;
 #pragma unroll
-                    for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
-                    s2 = wave_sum(s2 * w2);
-                    if (lane == ab2) mine = s2;
+                        for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
+                        s2 = wave_sum(s2 * w2);
+                        if (lane == ab2) mine = s2;
+                    }
+                    if (lane < NAB) atomic_add_f64(&Jm[(B.aoi + lane / NJ) * n + B.aoj + lane % NJ], mine);
+                } else if (valid) {
+#pragma unroll
+                    for (int ab2 = 0; ab2 < NAB; ++ab2) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
+                        atomic_add_f64(&Jm[(B.aoi + ab2 / NJ) * n + B.aoj + ab2 % NJ], w2 * s2);
+                    }
                 }
-                if (lane < NAB) atomic_add_f64(&Jm[(B.aoi + lane / NJ) * n + B.aoj + lane % NJ], mine);
                 if (valid) {
 #pragma unroll
                     for (int cd2 = 0; cd2 < NCD; ++cd2) {
@@ -490,6 +526,48 @@ __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
     }
 }
 
+// Tiles: one wave per tile of 64 kets of one bra.
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+__global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
+    const int lane = __lane_id();
+    if constexpr (MODE == MODE_JK) {
+        const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+        if (wave >= a.ntiles) return;
+        const int i = tile_bra(a.tile_off, a.nbra, wave);
+        const int j = (wave - a.tile_off[i]) * 64 + lane;
+        const int cnt = a.bra_cnt[i];
+        bool valid = j < cnt;
+        const int bra = a.bra_list[i];
+        const int ket = a.ket_list[valid ? j : cnt - 1];
+        const PairRec &B = a.pairs[bra];
+        const PairRec &Kt = a.pairs[ket];
+        const double wq = pair_weight(bra, ket, B, Kt);
+        if (a.sel == SEL_LOW) {
+            const bool hi = valid && above_threshold(a, B, Kt);
+            list_append(a, hi, bra, ket);
+            valid = valid && !hi;
+        }
+        k1_body<LI, LJ, LK, LL, R, MODE_JK>(a, bra, ket, valid, wq, 0);
+    } else if constexpr (MODE == MODE_EXPORT) {
+        const int g = blockIdx.x * 256 + threadIdx.x;
+        const bool valid = g < a.nq;
+        const int gg = valid ? g : a.nq - 1;
+        k1_body<LI, LJ, LK, LL, R, MODE_EXPORT>(a, a.q_bra[gg], a.q_ket[gg], valid, 1.0, g);
+    } else {
+        // persistent pass over the appended list; whole waves step together
+        const int cnt = min(*a.list_count, a.nq);
+        const int stride = gridDim.x * 256;
+        for (int g0 = blockIdx.x * 256 + (threadIdx.x & ~63); g0 < cnt; g0 += stride) {
+            const int g = g0 + lane;
+            const bool valid = g < cnt;
+            const int gg = valid ? g : cnt - 1;
+            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
+            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
+            k1_body<LI, LJ, LK, LL, R, MODE_LIST>(a, bra, ket, valid, wq, 0);
+        }
+    }
+}
+
 // ===========================================================================
 // Family 2: a lane group per quartet.  Lane slot (a, c) owns the elements
 // (a b | c d) for all b in the current pass's chunk and all d.  Per
@@ -528,53 +606,25 @@ struct K2Cfg {
     }
 };
 
+// One wave (the whole workgroup) handles QW quartets; every lane calls this
+// with its quartet's (bra, ket), so the barriers inside are uniform.
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
-__global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
+__device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, int bra, int ket, bool valid, double wq,
+                                        int64_t gq) {
     using C = Cls<LI, LJ, LK, LL>;
     using F = K2Cfg<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, S = C::S;
     constexpr int QW = F::QW, LPQ = F::LPQ, SPL = F::SPL, CB = F::CB, NPASS = F::NPASS;
-    __shared__ R tabs[QW * F::TAB];
-    __shared__ double dig[QW * F::DIG];
-
     const int lane = threadIdx.x;
-    const int q = QW > 1 ? lane / LPQ : 0;          // quartet of this lane
-    const int sl = QW > 1 ? lane % LPQ : lane;      // lane index within its quartet
-    const bool lane_used = q < QW;                  // lanes beyond QW*LPQ idle
+    const int q = QW > 1 ? lane / LPQ : 0;
+    const int sl = QW > 1 ? lane % LPQ : lane;
+    const bool lane_used = q < QW;
     const int qq = lane_used ? q : 0;
-
-    int bra, ket;
-    bool valid;
-    double wq = 1.0;
-    int gq;  // export slot
-    if constexpr (MODE == MODE_JK) {
-        const int wave = blockIdx.x;
-        const int i = tile_bra(a.tile_off, a.nbra, wave);
-        const int j = (wave - a.tile_off[i]) * QW + qq;
-        const int cnt = a.bra_cnt[i];
-        valid = lane_used && j < cnt;
-        bra = a.bra_list[i];
-        ket = a.ket_list[j < cnt ? j : cnt - 1];
-        if (a.same && j == i) wq *= 0.5;
-        gq = 0;
-    } else {
-        gq = blockIdx.x * QW + qq;
-        valid = lane_used && gq < a.nq;
-        const int gg = gq < a.nq ? gq : a.nq - 1;
-        bra = a.q_bra[gg];
-        ket = a.q_ket[gg];
-    }
     const PairRec B = a.pairs[bra];
     const PairRec Kt = a.pairs[ket];
-    if constexpr (MODE == MODE_JK) {
-        if (B.ish == B.jsh) wq *= 0.5;
-        if (Kt.ish == Kt.jsh) wq *= 0.5;
-        valid = valid && selected(a, B, Kt);
-    }
     const int npb = MODE == MODE_JK ? a.npb : B.npp;
     const int npk = MODE == MODE_JK ? a.npk : Kt.npp;
-    const int npq = npb * npk;  // per quartet; uniform within a wave in JK mode
-    // the wave loops over the largest primitive count among its quartets
+    const int npq = npb * npk;
     int npq_max = npq;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) npq_max = max(npq_max, __shfl_xor(npq_max, off, 64));
@@ -582,7 +632,6 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
     R *tq = tabs + qq * F::TAB;
     double *dq = dig + qq * F::DIG;
 
-    // slot coordinates
     int sa[SPL], sc[SPL];
     bool sv[SPL];
 #pragma unroll
@@ -596,7 +645,6 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
     int base[SPL][3];
 #pragma unroll
     for (int k = 0; k < SPL; ++k) {
-        // runtime (a, c) -> Cartesian exponents via small switch-free loops
         int ae[3] = {0, 0, 0}, ce[3] = {0, 0, 0};
 #pragma unroll
         for (int t = 0; t < NI; ++t)
@@ -622,12 +670,12 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
 
         for (int ipq = 0; ipq < npq_max; ++ipq) {
             const bool has = ipq < npq;
-            const int ib = has ? ipq / npk : 0, ik = has ? ipq % npk : 0;
-            // tables are rebuilt per pass only when there is more than one
-            // primitive quartet in the wave; otherwise pass 0's survive
+            const int ib = has ? ipq % npb : 0, ik = has ? ipq / npb : 0;
+            // with a single primitive quartet per quartet the tables of
+            // pass 0 are reused by the later passes
             const bool build = pass == 0 || npq_max > 1;
             if (build) {
-                if (pass > 0 || ipq > 0) __syncthreads();
+                __syncthreads();
                 const PrimPair pb = a.pp[B.pp_off + ib];
                 const PrimPair pk = a.pp[Kt.pp_off + ik];
                 const PQuart<R> g = prim_quartet<R>(pb, pk);
@@ -675,7 +723,7 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
 #pragma unroll
             for (int k = 0; k < SPL; ++k) {
                 if (!(valid && sv[k])) continue;
-                double *o = a.out + (int64_t)gq * C::NC;
+                double *o = a.out + gq * C::NC;
 #pragma unroll
                 for (int bb = 0; bb < CB; ++bb) {
                     const int b = pass * CB + bb;
@@ -736,7 +784,6 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
                     if (a.do_k) atomicAdd(&dq[F::O_KIK + ia * NK + ic], wq * kik);
                 }
                 __syncthreads();
-                // flush the group's blocks to global memory
                 if (lane_used && valid) {
                     double *Jm = a.J + s * a.mstride;
                     double *Km = a.K + s * a.mstride;
@@ -755,6 +802,52 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
                     }
                 }
             }
+        }
+    }
+}
+
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+__global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
+    using F = K2Cfg<LI, LJ, LK, LL>;
+    constexpr int QW = F::QW, LPQ = F::LPQ;
+    __shared__ R tabs[QW * F::TAB];
+    __shared__ double dig[QW * F::DIG];
+    const int lane = threadIdx.x;
+    const int q = QW > 1 ? lane / LPQ : 0;
+    const int sl = QW > 1 ? lane % LPQ : lane;
+    const bool lane_used = q < QW;
+    const int qq = lane_used ? q : 0;
+    if constexpr (MODE == MODE_JK) {
+        const int wave = blockIdx.x;
+        const int i = tile_bra(a.tile_off, a.nbra, wave);
+        const int j = (wave - a.tile_off[i]) * QW + qq;
+        const int cnt = a.bra_cnt[i];
+        bool valid = lane_used && j < cnt;
+        const int bra = a.bra_list[i];
+        const int ket = a.ket_list[j < cnt ? j : cnt - 1];
+        const PairRec &B = a.pairs[bra];
+        const PairRec &Kt = a.pairs[ket];
+        const double wq = pair_weight(bra, ket, B, Kt);
+        if (a.sel == SEL_LOW) {
+            const bool hi = valid && above_threshold(a, B, Kt);
+            list_append(a, hi && sl == 0, bra, ket);
+            valid = valid && !hi;
+        }
+        k2_body<LI, LJ, LK, LL, R, MODE_JK>(a, tabs, dig, bra, ket, valid, wq, 0);
+    } else if constexpr (MODE == MODE_EXPORT) {
+        const int gq = blockIdx.x * QW + qq;
+        const bool valid = lane_used && gq < a.nq;
+        const int gg = gq < a.nq ? gq : a.nq - 1;
+        k2_body<LI, LJ, LK, LL, R, MODE_EXPORT>(a, tabs, dig, a.q_bra[gg], a.q_ket[gg], valid, 1.0, gq);
+    } else {
+        const int cnt = min(*a.list_count, a.nq);
+        for (int b0 = blockIdx.x * QW; b0 < cnt; b0 += gridDim.x * QW) {
+            const int gq = b0 + qq;
+            const bool valid = lane_used && gq < cnt;
+            const int gg = gq < cnt ? gq : cnt - 1;
+            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
+            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
+            k2_body<LI, LJ, LK, LL, R, MODE_LIST>(a, tabs, dig, bra, ket, valid, wq, 0);
         }
     }
 }

@@ -11,7 +11,9 @@ constexpr int LMAX_BUILT = 3;  // classes instantiated up to (ff|ff)
 using Launcher = hipError_t (*)(const JkArgs &, hipStream_t);
 
 struct ClassEntry {
-    Launcher jk64, jk32, ex64, ex32;
+    Launcher tiles[2][2];  // [family - 1][0: FP64, 1: FP32], quartets from tiles
+    Launcher list64[2];    // [family - 1], FP64 pass over the appended list
+    Launcher ex64, ex32;   // export (default family)
 };
 
 // Indexed by class_id(li, lj, lk, ll); zero-initialised, filled by the

@@ -11,17 +11,25 @@
 namespace jk {
 
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
-static hipError_t launch_one(const JkArgs &a, hipStream_t s) {
-    if constexpr (family(LI, LJ, LK, LL) == 1) {
-        const int grid = MODE == MODE_JK ? (a.ntiles + 3) / 4 : (a.nq + 255) / 256;
-        if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL((jk_k1<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(256), 0, s, a);
-    } else {
-        constexpr int QW = k2_qw(LI, LJ, LK, LL);
-        const int grid = MODE == MODE_JK ? a.ntiles : (a.nq + QW - 1) / QW;
-        if (grid <= 0) return hipSuccess;
-        hipLaunchKernelGGL((jk_k2<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(64), 0, s, a);
-    }
+static hipError_t launch_k1(const JkArgs &a, hipStream_t s) {
+    int grid;
+    if constexpr (MODE == MODE_JK) grid = (a.ntiles + 3) / 4;
+    else if constexpr (MODE == MODE_EXPORT) grid = (a.nq + 255) / 256;
+    else grid = std::min((a.nq + 255) / 256, 2048);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((jk_k1<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+static hipError_t launch_k2(const JkArgs &a, hipStream_t s) {
+    constexpr int QW = k2_qw(LI, LJ, LK, LL);
+    int grid;
+    if constexpr (MODE == MODE_JK) grid = a.ntiles;
+    else if constexpr (MODE == MODE_EXPORT) grid = (a.nq + QW - 1) / QW;
+    else grid = std::min((a.nq + QW - 1) / QW, 8192);
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL((jk_k2<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -30,10 +38,23 @@ static void reg_one() {
     constexpr int LI = JK_LI, LJ = JK_LJ;
     if constexpr (LK >= LL && (LK < LI || (LK == LI && LL <= LJ))) {
         ClassEntry &e = g_classes[class_id(LI, LJ, LK, LL)];
-        e.jk64 = &launch_one<LI, LJ, LK, LL, double, MODE_JK>;
-        e.jk32 = &launch_one<LI, LJ, LK, LL, float, MODE_JK>;
-        e.ex64 = &launch_one<LI, LJ, LK, LL, double, MODE_EXPORT>;
-        e.ex32 = &launch_one<LI, LJ, LK, LL, float, MODE_EXPORT>;
+        if constexpr (has_family1(LI, LJ, LK, LL)) {
+            e.tiles[0][0] = &launch_k1<LI, LJ, LK, LL, double, MODE_JK>;
+            e.tiles[0][1] = &launch_k1<LI, LJ, LK, LL, float, MODE_JK>;
+            e.list64[0] = &launch_k1<LI, LJ, LK, LL, double, MODE_LIST>;
+        }
+        if constexpr (has_family2(LI, LJ, LK, LL)) {
+            e.tiles[1][0] = &launch_k2<LI, LJ, LK, LL, double, MODE_JK>;
+            e.tiles[1][1] = &launch_k2<LI, LJ, LK, LL, float, MODE_JK>;
+            e.list64[1] = &launch_k2<LI, LJ, LK, LL, double, MODE_LIST>;
+        }
+        if constexpr (default_family(LI, LJ, LK, LL) == 1) {
+            e.ex64 = &launch_k1<LI, LJ, LK, LL, double, MODE_EXPORT>;
+            e.ex32 = &launch_k1<LI, LJ, LK, LL, float, MODE_EXPORT>;
+        } else {
+            e.ex64 = &launch_k2<LI, LJ, LK, LL, double, MODE_EXPORT>;
+            e.ex32 = &launch_k2<LI, LJ, LK, LL, float, MODE_EXPORT>;
+        }
     }
 }
 

@@ -72,6 +72,9 @@ def lib():
         L.jk_batch_destroy.restype = None
         L.jk_plan_profile.argtypes = [vp, i32]
         L.jk_plan_timings.argtypes = [vp, ctypes.POINTER(ClassTiming), i32, ctypes.POINTER(i32)]
+        L.jk_tune_set.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.jk_tune_get.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.jk_tune_load.argtypes = [ctypes.c_char_p]
         L.jk_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -196,6 +199,27 @@ def build(mol, D, cutoff=1e-13, precision="fp64", stream=None):
                           PRECISION[precision], ctypes.c_void_p(J.data_ptr()), ctypes.c_void_p(K.data_ptr()),
                           _stream_handle(stream)))
     return J, K
+
+
+def tune_set(li, lj, lk, ll, precision, family):
+    """Kernel family (1, 2; 0 = default) for one canonical class."""
+    _check(lib().jk_tune_set(li, lj, lk, ll, PRECISION[precision], family))
+
+
+def tune_get(li, lj, lk, ll, precision):
+    """(family a new plan would use, bit mask of built families)."""
+    f, m = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().jk_tune_get(li, lj, lk, ll, PRECISION[precision], ctypes.byref(f), ctypes.byref(m)))
+    return f.value, m.value
+
+
+def tune_load(path):
+    _check(lib().jk_tune_load(os.fsencode(path)))
+
+
+def canonical_classes(lmax=3):
+    return [(i, j, k, l) for i in range(lmax + 1) for j in range(i + 1) for k in range(i + 1)
+            for l in range(k + 1) if k < i or (k == i and l <= j)]
 
 
 def rys_eval(n: int, T, precision="fp64"):
