@@ -166,17 +166,19 @@ int jk_boys_eval(int32_t m, const double *T_host, int32_t count, int32_t precisi
  * Per-kernel timing (measurement support).  While enabled, jk_execute
  * records a HIP event on its stream before and after every class-kernel
  * launch, waits for the last one before returning, and adds each launch's
- * duration to the class's running total.  jk_plan_profile(plan, 1) resets
- * the totals; jk_plan_timings copies up to cap entries (one per class and
- * precision that ran) and stores the number available in *count.
+ * duration to the running total of its (class, precision, kind) entry.
+ * jk_plan_profile(plan, 1) resets the totals; jk_plan_timings copies up to
+ * cap entries (those that ran) and stores the number available in *count.
  */
 typedef struct {
     int32_t li, lj, lk, ll;     /* angular momenta of the class */
     int32_t npb, npk;           /* primitive pairs per bra / ket pair */
     int32_t precision;          /* JK_FP64 or JK_FP32 */
-    int32_t launches;           /* launches summed into ms */
-    int64_t nquartets;          /* significant unique quartets of the class */
-    double model_flops;         /* algorithmic FLOPs of one launch, nset = 1 */
+    int32_t launches;           /* launches summed into ms (one per build) */
+    int32_t family;             /* kernel family (1, 2) */
+    int32_t kind;               /* 0 tiles, 1 row mode, 2 list (FP64 part of the mixed split) */
+    int64_t nquartets;          /* quartets processed, summed over the launches (0 for kind 2) */
+    double model_flops;         /* their algorithmic FLOPs (nset = 1), summed likewise */
     double ms;                  /* summed kernel time */
 } jk_class_timing;
 
@@ -190,13 +192,18 @@ int jk_plan_timings(const jk_plan *plan, jk_class_timing *out, int32_t cap, int3
  * block in registers, 2 = a lane group per quartet with 2-D integrals in
  * LDS.  jk_tune_set picks the family for one class and precision (JK_FP64
  * or JK_FP32; family 0 restores the built-in default); plans read the table
- * when they are created.  At load time the library reads tune_gfx950.txt
- * next to itself (or the file named by JK_TUNE_DB): one
- * "li lj lk ll precision family" line per entry, '#' comments.
+ * when they are created.  jk_tune_set_row controls row mode for one class
+ * and precision (0 default = allowed, 1 allowed, 2 off): in row mode a
+ * workgroup walks a whole long ket prefix of one bra and keeps the bra's K
+ * rows in LDS, so most J/K updates stay out of global atomics.  At load time
+ * the library reads tune_gfx950.txt next to itself (or the file named by
+ * JK_TUNE_DB): one "li lj lk ll precision family [row]" line per entry,
+ * '#' comments.
  * jk_tune_get reports the family a new plan would use and a bit mask of
  * the built families (1: family 1, 2: family 2).
  */
 int jk_tune_set(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family);
+int jk_tune_set_row(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t row);
 int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t *family,
                 int32_t *available);
 int jk_tune_load(const char *path);

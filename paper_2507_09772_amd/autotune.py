@@ -22,12 +22,13 @@ sys.path.insert(0, os.path.dirname(HERE))
 OUT = os.path.join(HERE, "tune_gfx950.txt")
 
 
-def measure(jk, synth, torch, names, precision, family, steps=2):
+def measure(jk, synth, torch, names, precision, family, row, steps=2):
     """Per angular class total ms with every class forced to ``family``
-    where built (default elsewhere)."""
+    where built (default elsewhere) and row mode on (1) or off (2)."""
     for c in jk.canonical_classes():
         _, avail = jk.tune_get(*c, precision)
         jk.tune_set(*c, precision, family if avail & family else 0)
+        jk.tune_set_row(*c, precision, row)
     tot = collections.defaultdict(float)
     for name in names:
         wl = synth.workload(name)
@@ -39,10 +40,9 @@ def measure(jk, synth, torch, names, precision, family, steps=2):
         for _ in range(steps):
             plan.execute(D, J, K, precision=precision)
         torch.cuda.synchronize()
-        want = jk.JK_FP32 if precision == "fp32" else jk.JK_FP64
         for t in plan.timings():
-            if t.precision == want:
-                tot[(t.li, t.lj, t.lk, t.ll)] += t.ms / t.launches
+            # every (class, precision, kind) entry has one launch per build
+            tot[(t.li, t.lj, t.lk, t.ll)] += t.ms / steps
         plan.close()
     return tot
 
@@ -56,23 +56,25 @@ def main():
 
     from paper_2507_09772_amd import jk, synth
     lines = ["# kernel family per (class, precision), chosen by paper_2507_09772_amd/autotune.py",
-             f"# workloads: {' '.join(args.workloads)}; columns: li lj lk ll precision(0 fp64, 2 fp32) family"]
+             f"# workloads: {' '.join(args.workloads)}; columns: li lj lk ll precision(0 fp64, 2 fp32) family "
+             "row(1 on, 2 off)"]
     report = {}
     for precision in ("fp64", "fp32"):
-        t1 = measure(jk, synth, torch, args.workloads, precision, 1)
-        t2 = measure(jk, synth, torch, args.workloads, precision, 2)
+        t = {(f, r): measure(jk, synth, torch, args.workloads, precision, f, r) for f in (1, 2) for r in (1, 2)}
         for c in jk.canonical_classes():
             _, avail = jk.tune_get(*c, precision)
-            a, b = t1.get(c), t2.get(c)
-            if avail != 3 or a is None or b is None:
+            opts = {k: v.get(c) for k, v in t.items() if avail & k[0] and v.get(c) is not None}
+            if not opts:
                 continue
-            fam = 1 if a <= b else 2
-            report[f"{precision} ({c[0]}{c[1]}|{c[2]}{c[3]})"] = {"family1_ms": a, "family2_ms": b, "chosen": fam}
-            lines.append(f"{c[0]} {c[1]} {c[2]} {c[3]} {jk.PRECISION[precision]} {fam}")
-            print(f"{precision} ({c[0]}{c[1]}|{c[2]}{c[3]}): family1 {a:8.3f} ms  family2 {b:8.3f} ms -> {fam}",
-                  flush=True)
+            (fam, row), best = min(opts.items(), key=lambda kv: kv[1])
+            report[f"{precision} ({c[0]}{c[1]}|{c[2]}{c[3]})"] = {f"f{k[0]}r{k[1]}": v for k, v in opts.items()}
+            lines.append(f"{c[0]} {c[1]} {c[2]} {c[3]} {jk.PRECISION[precision]} {fam} {row}")
+            print(f"{precision} ({c[0]}{c[1]}|{c[2]}{c[3]}): " +
+                  "  ".join(f"f{k[0]}/{'row' if k[1] == 1 else 'tile'} {v:8.3f}" for k, v in sorted(opts.items())) +
+                  f"  -> family {fam} {'row' if row == 1 else 'tiles'}", flush=True)
         for c in jk.canonical_classes():
             jk.tune_set(*c, precision, 0)
+            jk.tune_set_row(*c, precision, 0)
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(json.dumps(report), flush=True)

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -30,6 +31,12 @@ using namespace jk;
 // Loaded from the shipped per-device file at library load, settable through
 // jk_tune_set, read by jk_plan_create.
 static int32_t g_tune[NCLS][2];
+// Row mode per (class, precision): 0 default (allowed), 1 allowed, 2 off.
+static int32_t g_row[NCLS][2];
+static void ensure_tuning();
+
+// Bras with at least this many kets run in row mode (one workgroup each).
+static const int ROW_MIN_KETS = 192;
 
 // ---------------------------------------------------------------------------
 // errors
@@ -263,7 +270,14 @@ struct DevBuf {
 struct ClassTask {
     int li, lj, lk, ll;
     int bt, kt, same, npb, npk, nbra;
+    // row mode: long bras (positions into d_bra / d_cnt) and the short rest
+    int nrow = 0, nsbra = 0, nstiles[2] = {0, 0};
+    int64_t nq_row = 0;  // quartets of the long bras
+    int32_t *d_row = nullptr, *d_sbra = nullptr, *d_scnt = nullptr, *d_stile[2] = {nullptr, nullptr};
+    int ncolK = 0, ncolL = 0, seg_same = 0;
+    const int32_t *d_tshK = nullptr, *d_tshL = nullptr;
     int fam[2];          // family per precision (0 FP64, 1 FP32)
+    bool row_ok[2];      // row mode allowed per precision
     int ntiles[2];       // per family - 1
     int64_t nq, npq, list_off;
     double flops;
@@ -287,7 +301,9 @@ struct jk_plan {
     double *d_Jc = nullptr, *d_Kc = nullptr, *d_Dc = nullptr;
     int scratch_nset = 0, dc_nset = 0;
     int32_t *d_list = nullptr, *d_list_cnt = nullptr;  // mixed split
+    int32_t *d_tpos = nullptr;                         // shell -> index within its type
     bool last_mixed = false;
+    bool no_row = false;  // JK_NO_ROW=1 in the environment: tiles only (A/B measurements)
     float *d_dmax = nullptr;
     Tables tab{};
     jk_stats stats{};
@@ -295,7 +311,7 @@ struct jk_plan {
     // per-kernel timing
     bool profile = false;
     std::vector<hipEvent_t> events;
-    std::vector<jk_class_timing> timing;  // [2 * class + (FP32 ? 1 : 0)]
+    std::vector<jk_class_timing> timing;  // [(2 * class + (FP32 ? 1 : 0)) * 3 + kind]
 
     template <typename T>
     int alloc(T **p, size_t n) {
@@ -373,6 +389,7 @@ static int launch_export(jk_plan *P, int li, int lj, int lk, int ll, int precisi
 
 extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **out) {
     if (!out) return fail(JK_EINVAL, "out is NULL");
+    ensure_tuning();
     *out = nullptr;
     int rc = validate_basis(basis);
     if (rc) return rc;
@@ -383,6 +400,10 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
     std::unique_ptr<jk_plan> guard(P);
     HIPCHK(hipGetDevice(&P->device));
     if ((rc = tables_for_device(&P->tab))) return rc;
+    {
+        const char *nr = getenv("JK_NO_ROW");
+        P->no_row = nr && nr[0] == '1';
+    }
     const int ns = P->ns = basis->nshell;
     P->natom = basis->natom;
     P->sph = basis->spherical;
@@ -507,6 +528,17 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
         for (int p : v) sortedq[pt].push_back(P->hpairs[p].q);
         if (!v.empty() && (rc = P->put(&d_sorted[pt], v))) return rc;
     }
+    // shells of each type (the compressed column segments of row mode)
+    std::vector<std::vector<int32_t>> tsh(ntype);
+    std::vector<int32_t> tpos(ns);
+    for (int i = 0; i < ns; ++i) {
+        tpos[i] = (int32_t)tsh[stype[i]].size();
+        tsh[stype[i]].push_back(i);
+    }
+    std::vector<int32_t *> d_tsh(ntype, nullptr);
+    for (int t = 0; t < ntype; ++t)
+        if ((rc = P->put(&d_tsh[t], tsh[t]))) return rc;
+    if ((rc = P->put(&P->d_tpos, tpos))) return rc;
     // classes: unordered pairs of pair types, bra = larger (l1, l2), ties by type index
     auto lkey = [&](int pt) { const PairRec &r = P->hpairs[ptype_first[pt]]; return std::make_pair(P->l[r.ish], P->l[r.jsh]); };
     int64_t nq_tot = 0, npq_tot = 0;
@@ -529,6 +561,7 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 if (f < 1 || f > 2 || !avail[f - 1]) f = default_family(c.li, c.lj, c.lk, c.ll);
                 if (!avail[f - 1]) f = 3 - f;
                 c.fam[pr] = f;
+                c.row_ok[pr] = g_row[class_id(c.li, c.lj, c.lk, c.ll)][pr] != 2;
             }
             std::vector<int32_t> bl, cn, to[2];
             const auto &kq = sortedq[kt];
@@ -567,6 +600,46 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
             }
             c.d_ket = d_sorted[kt];
             c.list_off = nq_tot;
+            // row mode split: bras with a long ket prefix get a workgroup each
+            {
+                const int tK = ptype_key[kt] / ntype, tL = ptype_key[kt] % ntype;
+                c.ncolK = (int)tsh[tK].size() * ncart(c.lk);
+                c.ncolL = (int)tsh[tL].size() * ncart(c.ll);
+                c.seg_same = tK == tL;
+                c.d_tshK = d_tsh[tK];
+                c.d_tshL = d_tsh[tL];
+                std::vector<int32_t> rows, sb, scn, sto[2];
+                int64_t st[2] = {0, 0};
+                for (size_t i = 0; i < bl.size(); ++i) {
+                    if (cn[i] >= ROW_MIN_KETS) {
+                        rows.push_back((int32_t)i);
+                        c.nq_row += cn[i];
+                        continue;
+                    }
+                    sb.push_back(bl[i]);
+                    scn.push_back(cn[i]);
+                    for (int f = 0; f < 2; ++f) {
+                        sto[f].push_back((int32_t)st[f]);
+                        const int qpt = quartets_per_tile(f + 1, c.li, c.lj, c.lk, c.ll);
+                        st[f] += (cn[i] + qpt - 1) / qpt;
+                    }
+                }
+                c.nrow = (int)rows.size();
+                c.nsbra = (int)sb.size();
+                if (c.nrow > 0 && (ce.row[0][0] || ce.row[1][0])) {
+                    if ((rc = P->put(&c.d_row, rows))) return rc;
+                    if (c.nsbra > 0) {
+                        if ((rc = P->put(&c.d_sbra, sb)) || (rc = P->put(&c.d_scnt, scn))) return rc;
+                        for (int f = 0; f < 2; ++f) {
+                            c.nstiles[f] = (int)st[f];
+                            if (avail[f] && (rc = P->put(&c.d_stile[f], sto[f]))) return rc;
+                        }
+                    }
+                } else {
+                    c.nrow = 0;
+                    c.nq_row = 0;
+                }
+            }
             nq_tot += c.nq;
             npq_tot += c.npq;
             flops_tot += c.flops;
@@ -632,7 +705,7 @@ static bool valid_class(int li, int lj, int lk, int ll) {
            (lk < li || (lk == li && ll <= lj));
 }
 
-extern "C" int jk_tune_set(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family) {
+static int tune_set_impl(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family) {
     if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
     if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
     if (family < 0 || family > 2) return fail(JK_EINVAL, "family must be 0, 1 or 2");
@@ -642,8 +715,27 @@ extern "C" int jk_tune_set(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32
     return 0;
 }
 
+static int tune_set_row_impl(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t row) {
+    if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
+    if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
+    if (row < 0 || row > 2) return fail(JK_EINVAL, "row must be 0 (default), 1 (allowed) or 2 (off)");
+    g_row[class_id(li, lj, lk, ll)][precision == JK_FP32 ? 1 : 0] = row;
+    return 0;
+}
+
+extern "C" int jk_tune_set(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family) {
+    ensure_tuning();
+    return tune_set_impl(li, lj, lk, ll, precision, family);
+}
+
+extern "C" int jk_tune_set_row(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t row) {
+    ensure_tuning();
+    return tune_set_row_impl(li, lj, lk, ll, precision, row);
+}
+
 extern "C" int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t *family,
                            int32_t *available) {
+    ensure_tuning();
     if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
     if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
     const ClassEntry &e = g_classes[class_id(li, lj, lk, ll)];
@@ -653,7 +745,7 @@ extern "C" int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32
     return 0;
 }
 
-extern "C" int jk_tune_load(const char *path) {
+static int tune_load_impl(const char *path) {
     if (!path) return fail(JK_EINVAL, "path is NULL");
     FILE *f = fopen(path, "r");
     if (!f) return fail(JK_EINVAL, "cannot open %s", path);
@@ -662,12 +754,14 @@ extern "C" int jk_tune_load(const char *path) {
     while (fgets(line, sizeof line, f)) {
         ++lineno;
         if (line[0] == '#' || line[0] == '\n') continue;
-        int li, lj, lk, ll, pr, fam;
-        if (sscanf(line, "%d %d %d %d %d %d", &li, &lj, &lk, &ll, &pr, &fam) != 6) {
+        int li, lj, lk, ll, pr, fam, row = 0;
+        const int got = sscanf(line, "%d %d %d %d %d %d %d", &li, &lj, &lk, &ll, &pr, &fam, &row);
+        if (got != 6 && got != 7) {
             fclose(f);
-            return fail(JK_EINVAL, "%s:%d: expected 'li lj lk ll precision family'", path, lineno);
+            return fail(JK_EINVAL, "%s:%d: expected 'li lj lk ll precision family [row]'", path, lineno);
         }
-        const int rc = jk_tune_set(li, lj, lk, ll, pr, fam);
+        int rc = tune_set_impl(li, lj, lk, ll, pr, fam);
+        if (!rc) rc = tune_set_row_impl(li, lj, lk, ll, pr, row);
         if (rc) { fclose(f); return rc; }
         ++n;
     }
@@ -675,8 +769,13 @@ extern "C" int jk_tune_load(const char *path) {
     return 0;
 }
 
-// The shipped table for this device sits next to the library.
-__attribute__((constructor)) static void load_default_tuning() {
+// The shipped table for this device sits next to the library.  It is read
+// once, on the first plan creation or tuning call: the kernel units register
+// their classes from static initialisers, which must have run before the
+// table's entries can be checked against the built families.
+static std::once_flag g_tune_once;
+
+static void load_default_tuning() {
     const char *env = getenv("JK_TUNE_DB");
     std::string path;
     if (env && *env) {
@@ -691,7 +790,16 @@ __attribute__((constructor)) static void load_default_tuning() {
     FILE *f = fopen(path.c_str(), "r");
     if (!f) return;
     fclose(f);
-    (void)jk_tune_load(path.c_str());
+    const std::string keep = g_err;
+    if (tune_load_impl(path.c_str()) != 0) fprintf(stderr, "libjk: tuning table %s ignored: %s\n", path.c_str(), g_err.c_str());
+    g_err = keep;
+}
+
+static void ensure_tuning() { std::call_once(g_tune_once, load_default_tuning); }
+
+extern "C" int jk_tune_load(const char *path) {
+    ensure_tuning();
+    return tune_load_impl(path);
 }
 
 extern "C" int jk_plan_schwarz(const jk_plan *P, double *Q) {
@@ -784,9 +892,9 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     }
     P->last_mixed = precision == JK_MIXED;
     // launches in order: (class, precision) -> timing slot
-    std::vector<int> slots;
+    std::vector<std::pair<int, int64_t>> slots;  // (timing slot, quartets of the launch)
     int nev = 0;
-    auto mark = [&](int slot) -> int {
+    auto mark = [&](int slot, int64_t nq) -> int {
         if (!P->profile) return 0;
         if ((int)P->events.size() <= nev) {
             hipEvent_t ev;
@@ -794,54 +902,77 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
             P->events.push_back(ev);
         }
         HIPCHK(hipEventRecord(P->events[nev++], s));
-        if (slot >= 0) slots.push_back(slot);
+        if (slot >= 0) slots.push_back({slot, nq});
         return 0;
     };
+    a.tpos = P->d_tpos;
+    a.aoc = P->maps.aoc;
     for (size_t ci = 0; ci < P->cls.size(); ++ci) {
         const ClassTask &c = P->cls[ci];
         const ClassEntry &e = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
-        a.bra_list = c.d_bra;
         a.ket_list = c.d_ket;
-        a.bra_cnt = c.d_cnt;
-        a.nbra = c.nbra;
         a.same = c.same;
         a.npb = c.npb;
         a.npk = c.npk;
-        if (precision == JK_FP64) {
-            const int f = c.fam[0];
-            a.tile_off = c.d_tile[f - 1];
-            a.ntiles = c.ntiles[f - 1];
-            a.sel = SEL_ALL;
-            if ((rc = mark((int)(2 * ci)))) return rc;
-            HIPCHK(e.tiles[f - 1][0](a, s));
+        const int pr = precision == JK_FP64 ? 0 : 1;
+        const int f = c.fam[pr];
+        a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
+        a.list = P->d_list ? P->d_list + 2 * c.list_off : nullptr;
+        a.list_count = P->d_list_cnt ? P->d_list_cnt + ci : nullptr;
+        a.nq = (int32_t)c.nq;
+        const int slot = (int)(2 * ci + pr) * 3;  // + kind
+        const size_t row_lds =
+            row_lds_bytes(e, f, pr, c.li, c.lj, nset, c.ncolK + (c.seg_same ? 0 : c.ncolL));
+        const bool rowmode = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] && row_lds <= (size_t)ROW_LDS_MAX && !P->no_row;
+        if (rowmode) {
+            // long bras: one workgroup each; the short rest as tiles
+            a.bra_list = c.d_bra;
+            a.bra_cnt = c.d_cnt;
+            a.row_pos = c.d_row;
+            a.nrow = c.nrow;
+            a.tshK = c.d_tshK;
+            a.tshL = c.d_tshL;
+            a.ncolK = c.ncolK;
+            a.ncolL = c.ncolL;
+            a.seg_same = c.seg_same;
+            if ((rc = mark(slot + 1, c.nq_row))) return rc;
+            HIPCHK(e.row[f - 1][pr](a, s));
+            a.bra_list = c.d_sbra;
+            a.bra_cnt = c.d_scnt;
+            a.nbra = c.nsbra;
+            a.tile_off = c.d_stile[f - 1];
+            a.ntiles = c.nstiles[f - 1];
         } else {
-            // FP32 tile pass (in the mixed split it diverts large-bound
-            // quartets to the list), then the FP64 list pass
-            const int f = c.fam[1];
+            a.bra_list = c.d_bra;
+            a.bra_cnt = c.d_cnt;
+            a.nbra = c.nbra;
             a.tile_off = c.d_tile[f - 1];
             a.ntiles = c.ntiles[f - 1];
-            a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
-            a.list = P->d_list + 2 * c.list_off;
-            a.list_count = P->d_list_cnt + ci;
-            a.nq = (int32_t)c.nq;
-            if ((rc = mark((int)(2 * ci + 1)))) return rc;
-            HIPCHK(e.tiles[f - 1][1](a, s));
-            if (precision == JK_MIXED) {
-                const int f64 = c.fam[0];
-                if ((rc = mark((int)(2 * ci)))) return rc;
-                HIPCHK(e.list64[f64 - 1](a, s));
-            }
+        }
+        if (a.ntiles > 0) {
+            if ((rc = mark(slot, rowmode ? c.nq - c.nq_row : c.nq))) return rc;
+            HIPCHK(e.tiles[f - 1][pr](a, s));
+        }
+        if (precision == JK_MIXED) {
+            // the FP32 passes above diverted large-bound quartets to the
+            // list; the FP64 list pass follows
+            const int f64 = c.fam[0];
+            if ((rc = mark((int)(2 * ci) * 3 + 2, 0))) return rc;
+            HIPCHK(e.list64[f64 - 1](a, s));
         }
     }
     if (P->profile) {
-        if ((rc = mark(-1))) return rc;
+        if ((rc = mark(-1, 0))) return rc;
         HIPCHK(hipEventSynchronize(P->events[nev - 1]));
         for (size_t k = 0; k < slots.size(); ++k) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, P->events[k], P->events[k + 1]));
-            jk_class_timing &t = P->timing[slots[k]];
+            jk_class_timing &t = P->timing[slots[k].first];
+            const ClassTask &c = P->cls[slots[k].first / 6];
             t.ms += ms;
             t.launches += 1;
+            t.nquartets += slots[k].second;
+            t.model_flops += c.flops * (double)slots[k].second / (double)c.nq;
         }
     }
     const int acc = (flags & JK_ACCUMULATE) ? 1 : 0;
@@ -855,17 +986,18 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
 extern "C" int jk_plan_profile(jk_plan *P, int32_t enable) {
     if (!P) return fail(JK_EINVAL, "plan is NULL");
     P->profile = enable != 0;
-    P->timing.assign(2 * P->cls.size(), jk_class_timing{});
+    P->timing.assign(6 * P->cls.size(), jk_class_timing{});
     for (size_t ci = 0; ci < P->cls.size(); ++ci)
-        for (int k = 0; k < 2; ++k) {
-            const ClassTask &c = P->cls[ci];
-            jk_class_timing &t = P->timing[2 * ci + k];
-            t.li = c.li; t.lj = c.lj; t.lk = c.lk; t.ll = c.ll;
-            t.npb = c.npb; t.npk = c.npk;
-            t.precision = k ? JK_FP32 : JK_FP64;
-            t.nquartets = c.nq;
-            t.model_flops = c.flops;
-        }
+        for (int k = 0; k < 2; ++k)
+            for (int kind = 0; kind < 3; ++kind) {
+                const ClassTask &c = P->cls[ci];
+                jk_class_timing &t = P->timing[(2 * ci + k) * 3 + kind];
+                t.li = c.li; t.lj = c.lj; t.lk = c.lk; t.ll = c.ll;
+                t.npb = c.npb; t.npk = c.npk;
+                t.precision = (k && kind != 2) ? JK_FP32 : JK_FP64;
+                t.family = kind == 2 ? c.fam[0] : c.fam[k];
+                t.kind = kind;
+            }
     return 0;
 }
 

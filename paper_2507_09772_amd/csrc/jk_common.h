@@ -72,6 +72,9 @@ JK_HD constexpr int quartets_per_tile(int fam, int li, int lj, int lk, int ll) {
 // with digestion (the FP64 part of the mixed split), or an explicit list
 // whose blocks are written out (Schwarz diagonal, test hook).
 enum { MODE_JK = 0, MODE_EXPORT = 1, MODE_LIST = 2 };
+// Row mode (family 1): one workgroup per bra with a long ket prefix; K rows
+// of the bra's two shells accumulate in LDS over column-compressed segments
+// (the columns of the ket shell types only) and are flushed once.
 // SEL_LOW: FP32 tile pass of the mixed split; quartets whose bound reaches
 // the threshold are appended to the list for the FP64 list pass instead.
 enum { SEL_ALL = 0, SEL_LOW = 1 };
@@ -99,6 +102,13 @@ struct JkArgs {
     // reads them back (nq is the capacity)
     int32_t *list;
     int32_t *list_count;
+    // row mode: list positions of the long bras; column segments of the ket
+    // shell types (shells of each type in order; tpos = index of a shell
+    // within its type); segment L aliases segment K when the types match
+    const int32_t *row_pos;
+    int32_t nrow;
+    const int32_t *tpos, *tshK, *tshL, *aoc;
+    int32_t ncolK, ncolL, seg_same;
     // densities and results (Cartesian, [nset][nao][nao])
     const double *D;
     double *J, *K;

@@ -242,6 +242,20 @@ struct Cls {
     }
 };
 
+// Lane index within the wave.  Taken from threadIdx rather than mbcnt:
+// mbcnt counts the active lanes below the current one, which differs from
+// the lane index when the compiler evaluates it under a partial EXEC mask.
+__device__ __forceinline__ int lane_index() { return (int)(threadIdx.x & 63u); }
+
+// Orders a wave's LDS writes before its later LDS reads by other lanes of
+// the same wave (the LDS tables of family 2 are private to one wave, so no
+// workgroup barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __device__ __forceinline__ void atomic_add_f64(double *p, T v) {
     unsafeAtomicAdd(p, (double)v);
@@ -283,7 +297,7 @@ __device__ __forceinline__ float dmax6(const JkArgs &a, const PairRec &B, const 
 __device__ __forceinline__ void list_append(const JkArgs &a, bool push, int bra, int ket) {
     const unsigned long long m = __ballot(push);
     if (m == 0ull) return;
-    const int lane = __lane_id();
+    const int lane = lane_index();
     int base = 0;
     if (lane == 0) base = atomicAdd(a.list_count, (int)__popcll(m));
     base = __shfl(base, 0, 64);
@@ -350,19 +364,14 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
 // registers; digestion reduces J_IJ across the wave when the bra is uniform
 // (tiles) and sends the other blocks straight to FP64 atomics.
 // ===========================================================================
-template <int LI, int LJ, int LK, int LL, typename R, int MODE>
-__device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool valid, double wq, int64_t gout) {
+// Contracted Cartesian block of one quartet into V (registers).
+template <int LI, int LJ, int LK, int LL, typename R>
+__device__ __forceinline__ void k1_compute(const JkArgs &a, const PairRec &B, const PairRec &Kt, int npb, int npk,
+                                           R (&V)[ncart4(LI, LJ, LK, LL)]) {
     using C = Cls<LI, LJ, LK, LL>;
-    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NAB = C::NAB, NCD = C::NCD, NR = C::NR;
-    constexpr bool BRA_UNIFORM = MODE == MODE_JK;
-    const int lane = __lane_id();
-    const PairRec B = a.pairs[bra];
-    const PairRec Kt = a.pairs[ket];
-    R V[NAB * NCD];
+    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR;
 #pragma unroll
-    for (int e = 0; e < NAB * NCD; ++e) V[e] = (R)0;
-    const int npb = BRA_UNIFORM ? a.npb : B.npp;
-    const int npk = MODE == MODE_JK ? a.npk : Kt.npp;
+    for (int e = 0; e < C::NC; ++e) V[e] = (R)0;
     const R ab[3] = {(R)B.ab[0], (R)B.ab[1], (R)B.ab[2]};
     const R cd[3] = {(R)Kt.ab[0], (R)Kt.ab[1], (R)Kt.ab[2]};
     // ket primitive outer (one vector load each), bra primitive inner (the
@@ -406,6 +415,18 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
             }
         }
     }
+}
+
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+__device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool valid, double wq, int64_t gout) {
+    using C = Cls<LI, LJ, LK, LL>;
+    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NAB = C::NAB, NCD = C::NCD;
+    constexpr bool BRA_UNIFORM = MODE == MODE_JK;
+    const int lane = lane_index();
+    const PairRec B = a.pairs[bra];
+    const PairRec Kt = a.pairs[ket];
+    R V[C::NC];
+    k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, BRA_UNIFORM ? a.npb : B.npp, MODE == MODE_JK ? a.npk : Kt.npp, V);
     if constexpr (MODE == MODE_EXPORT) {
         if (valid) {
             double *o = a.out + gout * (NAB * NCD);
@@ -529,7 +550,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
 // Tiles: one wave per tile of 64 kets of one bra.
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
 __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
-    const int lane = __lane_id();
+    const int lane = lane_index();
     if constexpr (MODE == MODE_JK) {
         const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (wave >= a.ntiles) return;
@@ -564,6 +585,168 @@ __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
             const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
             const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
             k1_body<LI, LJ, LK, LL, R, MODE_LIST>(a, bra, ket, valid, wq, 0);
+        }
+    }
+}
+
+// Row mode: one workgroup of 256 lanes walks the whole ket prefix of one bra.
+// K'_IK, K'_IL (row block of shell I) and K'_JK, K'_JL (row block of J)
+// accumulate in LDS over the compressed ket-type columns, J'_IJ in LDS, and
+// only J'_KL goes to global atomics per quartet.  Dynamic LDS layout, per
+// density: [NI rows | NJ rows] x ncols, then NAB for J'_IJ.
+template <int LI, int LJ, int LK, int LL, typename R>
+__global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
+    using C = Cls<LI, LJ, LK, LL>;
+    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NAB = C::NAB, NCD = C::NCD;
+    extern __shared__ double rowmem[];
+    const int tid = threadIdx.x, lane = lane_index();
+    const int i = a.row_pos[blockIdx.x];
+    const int cnt = a.bra_cnt[i];
+    const int bra = a.bra_list[i];
+    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
+    const int segL = a.seg_same ? 0 : a.ncolK;
+    const int per_set = (NI + NJ) * ncols + NAB;
+    for (int t = tid; t < per_set * a.nset; t += 256) rowmem[t] = 0.0;
+    __syncthreads();
+    const PairRec B = a.pairs[bra];
+    const int n = a.nao;
+    for (int j0 = 0; j0 < cnt; j0 += 256) {
+        const int j = j0 + tid;
+        bool valid = j < cnt;
+        const int ket = a.ket_list[valid ? j : cnt - 1];
+        const PairRec Kt = a.pairs[ket];
+        const double wq = pair_weight(bra, ket, B, Kt);
+        if (a.sel == SEL_LOW) {
+            const bool hi = valid && above_threshold(a, B, Kt);
+            list_append(a, hi, bra, ket);
+            valid = valid && !hi;
+        }
+        R V[C::NC];
+        k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, a.npb, a.npk, V);
+        const int cK = a.tpos[Kt.ish] * NK, cL = segL + a.tpos[Kt.jsh] * NL;
+        for (int s = 0; s < a.nset; ++s) {
+            const double *D = a.D + s * a.mstride;
+            double *rm = rowmem + s * per_set;
+            double *rI = rm, *rJ = rm + NI * ncols, *jij = rm + (NI + NJ) * ncols;
+            if (a.do_j) {
+                double dij[NAB], dkl[NCD];
+#pragma unroll
+                for (int i2 = 0; i2 < NI; ++i2)
+#pragma unroll
+                    for (int j2 = 0; j2 < NJ; ++j2) dij[i2 * NJ + j2] = D[(B.aoi + i2) * n + B.aoj + j2];
+#pragma unroll
+                for (int k = 0; k < NK; ++k)
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) dkl[k * NL + l] = D[(Kt.aoi + k) * n + Kt.aoj + l];
+                const double w2 = valid ? 2.0 * wq : 0.0;
+                double mine = 0.0;
+#pragma unroll
+                for (int ab2 = 0; ab2 < NAB; ++ab2) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
+                    s2 = wave_sum(s2 * w2);
+                    if (lane == ab2) mine = s2;
+                }
+                if (lane < NAB) atomicAdd(&jij[lane], mine);
+                if (valid) {
+                    double *Jm = a.J + s * a.mstride;
+#pragma unroll
+                    for (int cd2 = 0; cd2 < NCD; ++cd2) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int ab2 = 0; ab2 < NAB; ++ab2) s2 += (double)V[ab2 * NCD + cd2] * dij[ab2];
+                        atomic_add_f64(&Jm[(Kt.aoi + cd2 / NL) * n + Kt.aoj + cd2 % NL], w2 * s2);
+                    }
+                }
+            }
+            if (a.do_k && valid) {
+                double djl[NJ * NL], djk[NJ * NK], dil[NI * NL], dik[NI * NK];
+#pragma unroll
+                for (int j2 = 0; j2 < NJ; ++j2) {
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) djl[j2 * NL + l] = D[(B.aoj + j2) * n + Kt.aoj + l];
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) djk[j2 * NK + k] = D[(B.aoj + j2) * n + Kt.aoi + k];
+                }
+#pragma unroll
+                for (int i2 = 0; i2 < NI; ++i2) {
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) dil[i2 * NL + l] = D[(B.aoi + i2) * n + Kt.aoj + l];
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) dik[i2 * NK + k] = D[(B.aoi + i2) * n + Kt.aoi + k];
+                }
+#pragma unroll
+                for (int i2 = 0; i2 < NI; ++i2)
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int j2 = 0; j2 < NJ; ++j2)
+#pragma unroll
+                            for (int l = 0; l < NL; ++l)
+                                s2 += (double)V[((i2 * NJ + j2) * NK + k) * NL + l] * djl[j2 * NL + l];
+                        atomicAdd(&rI[i2 * ncols + cK + k], wq * s2);
+                    }
+#pragma unroll
+                for (int i2 = 0; i2 < NI; ++i2)
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int j2 = 0; j2 < NJ; ++j2)
+#pragma unroll
+                            for (int k = 0; k < NK; ++k)
+                                s2 += (double)V[((i2 * NJ + j2) * NK + k) * NL + l] * djk[j2 * NK + k];
+                        atomicAdd(&rI[i2 * ncols + cL + l], wq * s2);
+                    }
+#pragma unroll
+                for (int j2 = 0; j2 < NJ; ++j2)
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int i2 = 0; i2 < NI; ++i2)
+#pragma unroll
+                            for (int l = 0; l < NL; ++l)
+                                s2 += (double)V[((i2 * NJ + j2) * NK + k) * NL + l] * dil[i2 * NL + l];
+                        atomicAdd(&rJ[j2 * ncols + cK + k], wq * s2);
+                    }
+#pragma unroll
+                for (int j2 = 0; j2 < NJ; ++j2)
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int i2 = 0; i2 < NI; ++i2)
+#pragma unroll
+                            for (int k = 0; k < NK; ++k)
+                                s2 += (double)V[((i2 * NJ + j2) * NK + k) * NL + l] * dik[i2 * NK + k];
+                        atomicAdd(&rJ[j2 * ncols + cL + l], wq * s2);
+                    }
+            }
+        }
+    }
+    __syncthreads();
+    // flush nonzero entries to the global J', K'
+    for (int s = 0; s < a.nset; ++s) {
+        const double *rm = rowmem + s * per_set;
+        double *Jm = a.J + s * a.mstride;
+        double *Km = a.K + s * a.mstride;
+        for (int t = tid; t < per_set; t += 256) {
+            const double v = rm[t];
+            if (v == 0.0) continue;
+            if (t >= (NI + NJ) * ncols) {
+                const int e = t - (NI + NJ) * ncols;
+                atomic_add_f64(&Jm[(B.aoi + e / NJ) * n + B.aoj + e % NJ], v);
+                continue;
+            }
+            const int r = t / ncols, c = t % ncols;
+            const int row = r < NI ? B.aoi + r : B.aoj + (r - NI);
+            int col;
+            if (c < a.ncolK) col = a.aoc[a.tshK[c / NK]] + c % NK;
+            else col = a.aoc[a.tshL[(c - a.ncolK) / NL]] + (c - a.ncolK) % NL;
+            atomic_add_f64(&Km[row * n + col], v);
         }
     }
 }
@@ -606,16 +789,19 @@ struct K2Cfg {
     }
 };
 
-// One wave (the whole workgroup) handles QW quartets; every lane calls this
-// with its quartet's (bra, ket), so the barriers inside are uniform.
-template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+// One wave handles QW quartets with its own tables and digestion blocks;
+// all synchronisation inside is per wave, so the waves of a workgroup are
+// independent.  ROW: the four K blocks and J_IJ go to the
+// workgroup's shared K rows of the (uniform) bra instead (row mode), only
+// J_KL is flushed per quartet.
+template <int LI, int LJ, int LK, int LL, typename R, int MODE, bool ROW = false>
 __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, int bra, int ket, bool valid, double wq,
-                                        int64_t gq) {
+                                        int64_t gq, double *rows = nullptr, int ncols = 0, int segL = 0) {
     using C = Cls<LI, LJ, LK, LL>;
     using F = K2Cfg<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, S = C::S;
     constexpr int QW = F::QW, LPQ = F::LPQ, SPL = F::SPL, CB = F::CB, NPASS = F::NPASS;
-    const int lane = threadIdx.x;
+    const int lane = lane_index();
     const int q = QW > 1 ? lane / LPQ : 0;
     const int sl = QW > 1 ? lane % LPQ : lane;
     const bool lane_used = q < QW;
@@ -675,7 +861,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
             // pass 0 are reused by the later passes
             const bool build = pass == 0 || npq_max > 1;
             if (build) {
-                __syncthreads();
+                wave_sync();
                 const PrimPair pb = a.pp[B.pp_off + ib];
                 const PrimPair pk = a.pp[Kt.pp_off + ik];
                 const PQuart<R> g = prim_quartet<R>(pb, pk);
@@ -696,7 +882,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                     rys2d<LI, LJ, LK, LL, R>(c00, c00p, b00, b10, b01, abx, cdx, sc2,
                                              [&](int ia, int ib2, int ic, int id, R v) { dst[F::tix(ia, ib2, ic, id)] = v; });
                 }
-                __syncthreads();
+                wave_sync();
             }
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -734,11 +920,15 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
             }
         } else {
             const int n = a.nao;
+            // row mode: compressed K-row columns of this quartet's ket shells
+            const int cK = ROW ? a.tpos[Kt.ish] * NK : 0, cL = ROW ? segL + a.tpos[Kt.jsh] * NL : 0;
+            const int per_set = (NI + NJ) * ncols + NI * NJ;
             for (int s = 0; s < a.nset; ++s) {
                 const double *D = a.D + s * a.mstride;
-                __syncthreads();
+                double *rI = rows + s * per_set, *rJ = rI + NI * ncols, *rjij = rI + (NI + NJ) * ncols;
+                wave_sync();
                 for (int t = lane; t < QW * F::DIG; t += 64) dig[t] = 0.0;
-                __syncthreads();
+                wave_sync();
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
                     if (!(valid && sv[k])) continue;
@@ -771,23 +961,24 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                             kik += v * djl;
                             kil[d] += v * djk;
                             kjk += v * dil[d];
-                            if (a.do_k) atomicAdd(&dq[F::O_KJL + b * NL + d], wq * v * dik);
+                            if (a.do_k) atomicAdd(ROW ? &rJ[b * ncols + cL + d] : &dq[F::O_KJL + b * NL + d], wq * v * dik);
                         }
-                        if (a.do_j) atomicAdd(&dq[F::O_JIJ + ia * NJ + b], 2.0 * wq * jij);
-                        if (a.do_k) atomicAdd(&dq[F::O_KJK + b * NK + ic], wq * kjk);
+                        if (a.do_j) atomicAdd(ROW ? &rjij[ia * NJ + b] : &dq[F::O_JIJ + ia * NJ + b], 2.0 * wq * jij);
+                        if (a.do_k) atomicAdd(ROW ? &rJ[b * ncols + cK + ic] : &dq[F::O_KJK + b * NK + ic], wq * kjk);
                     }
 #pragma unroll
                     for (int d = 0; d < NL; ++d) {
                         if (a.do_j) atomicAdd(&dq[F::O_JKL + ic * NL + d], 2.0 * wq * jkl[d]);
-                        if (a.do_k) atomicAdd(&dq[F::O_KIL + ia * NL + d], wq * kil[d]);
+                        if (a.do_k) atomicAdd(ROW ? &rI[ia * ncols + cL + d] : &dq[F::O_KIL + ia * NL + d], wq * kil[d]);
                     }
-                    if (a.do_k) atomicAdd(&dq[F::O_KIK + ia * NK + ic], wq * kik);
+                    if (a.do_k) atomicAdd(ROW ? &rI[ia * ncols + cK + ic] : &dq[F::O_KIK + ia * NK + ic], wq * kik);
                 }
-                __syncthreads();
+                wave_sync();
                 if (lane_used && valid) {
                     double *Jm = a.J + s * a.mstride;
                     double *Km = a.K + s * a.mstride;
-                    for (int t = sl; t < F::DIG; t += LPQ) {
+                    const int t0 = ROW ? F::O_JKL : 0, t1 = ROW ? F::O_KIK : F::DIG;
+                    for (int t = t0 + sl; t < t1; t += LPQ) {
                         const double v = dq[t];
                         if (v == 0.0) continue;
                         int row, col;
@@ -848,6 +1039,82 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
             const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
             const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
             k2_body<LI, LJ, LK, LL, R, MODE_LIST>(a, tabs, dig, bra, ket, valid, wq, 0);
+        }
+    }
+}
+
+// Row mode for family 2: four independent waves per workgroup walk one bra's
+// ket prefix (interleaved by QW quartets), sharing the bra's K rows and J_IJ
+// in LDS; one workgroup barrier before the final flush.
+// Dynamic LDS: [nset][(NI+NJ) ncols + NI NJ] doubles, then 4 waves x
+// QW x DIG doubles, then 4 waves x QW x TAB reals.
+template <int LI, int LJ, int LK, int LL>
+struct K2RowLds {
+    using F = K2Cfg<LI, LJ, LK, LL>;
+    template <typename R>
+    static constexpr size_t fixed() { return 4 * (size_t)F::QW * (F::DIG * sizeof(double) + F::TAB * sizeof(R)); }
+    static constexpr size_t per_set(int ncols) {
+        return sizeof(double) * ((size_t)(ncart(LI) + ncart(LJ)) * ncols + (size_t)ncart(LI) * ncart(LJ));
+    }
+};
+
+template <int LI, int LJ, int LK, int LL, typename R>
+__global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
+    using C = Cls<LI, LJ, LK, LL>;
+    using F = K2Cfg<LI, LJ, LK, LL>;
+    constexpr int NI = C::NI, NJ = C::NJ, NAB = C::NAB;
+    constexpr int QW = F::QW, LPQ = F::LPQ;
+    extern __shared__ double smem2[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = lane_index();
+    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
+    const int segL = a.seg_same ? 0 : a.ncolK;
+    const int per_set = (NI + NJ) * ncols + NAB;
+    double *rows = smem2;
+    double *dig = rows + (size_t)per_set * a.nset + (size_t)wave * QW * F::DIG;
+    R *tabs = (R *)(rows + (size_t)per_set * a.nset + 4 * QW * F::DIG) + (size_t)wave * QW * F::TAB;
+    const int i = a.row_pos[blockIdx.x];
+    const int cnt = a.bra_cnt[i];
+    const int bra = a.bra_list[i];
+    for (int t = tid; t < per_set * a.nset; t += 256) rows[t] = 0.0;
+    __syncthreads();
+    const int q = QW > 1 ? lane / LPQ : 0;
+    const int sl = QW > 1 ? lane % LPQ : lane;
+    const bool lane_used = q < QW;
+    const int qq = lane_used ? q : 0;
+    const PairRec &B = a.pairs[bra];
+    for (int j0 = wave * QW; j0 < cnt; j0 += 4 * QW) {
+        const int j = j0 + qq;
+        bool valid = lane_used && j < cnt;
+        const int ket = a.ket_list[j < cnt ? j : cnt - 1];
+        const PairRec &Kt = a.pairs[ket];
+        const double wq = pair_weight(bra, ket, B, Kt);
+        if (a.sel == SEL_LOW) {
+            const bool hi = valid && above_threshold(a, B, Kt);
+            list_append(a, hi && sl == 0, bra, ket);
+            valid = valid && !hi;
+        }
+        k2_body<LI, LJ, LK, LL, R, MODE_JK, true>(a, tabs, dig, bra, ket, valid, wq, 0, rows, ncols, segL);
+    }
+    __syncthreads();
+    const int n = a.nao;
+    for (int s = 0; s < a.nset; ++s) {
+        const double *rm = rows + s * per_set;
+        double *Jm = a.J + s * a.mstride;
+        double *Km = a.K + s * a.mstride;
+        for (int t = tid; t < per_set; t += 256) {
+            const double v = rm[t];
+            if (v == 0.0) continue;
+            if (t >= (NI + NJ) * ncols) {
+                const int e = t - (NI + NJ) * ncols;
+                atomic_add_f64(&Jm[(B.aoi + e / NJ) * n + B.aoj + e % NJ], v);
+                continue;
+            }
+            const int r = t / ncols, c = t % ncols;
+            const int row = r < NI ? B.aoi + r : B.aoj + (r - NI);
+            int col;
+            if (c < a.ncolK) col = a.aoc[a.tshK[c / ncart(LK)]] + c % ncart(LK);
+            else col = a.aoc[a.tshL[(c - a.ncolK) / ncart(LL)]] + (c - a.ncolK) % ncart(LL);
+            atomic_add_f64(&Km[row * n + col], v);
         }
     }
 }

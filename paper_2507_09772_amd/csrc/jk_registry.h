@@ -14,7 +14,20 @@ struct ClassEntry {
     Launcher tiles[2][2];  // [family - 1][0: FP64, 1: FP32], quartets from tiles
     Launcher list64[2];    // [family - 1], FP64 pass over the appended list
     Launcher ex64, ex32;   // export (default family)
+    Launcher row[2][2];    // row mode, [family - 1][0: FP64, 1: FP32]
+    size_t row_fixed[2][2];  // row-mode LDS bytes besides the K rows, [family - 1][precision]
 };
+
+// LDS bytes of one row-mode workgroup: the fixed part plus nset copies of
+// the bra's K rows over ncols compressed columns and its J_IJ block.
+inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj, int nset, int ncols) {
+    return e.row_fixed[fam - 1][pr] +
+           sizeof(double) * (size_t)nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj));
+}
+
+// LDS budget of one row-mode workgroup (dynamic shared memory; gfx950 has
+// 160 KB per CU, kernels above 64 KB opt in through a function attribute).
+constexpr int ROW_LDS_MAX = 128 * 1024;
 
 // Indexed by class_id(li, lj, lk, ll); zero-initialised, filled by the
 // static initialisers of the kernel units when the library loads.

@@ -21,6 +21,42 @@ static hipError_t launch_k1(const JkArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int LI, int LJ, int LK, int LL, typename R>
+static hipError_t launch_row(const JkArgs &a, hipStream_t s) {
+    if (a.nrow <= 0) return hipSuccess;
+    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
+    const size_t lds = sizeof(double) * (size_t)a.nset *
+                       ((size_t)(ncart(LI) + ncart(LJ)) * ncols + (size_t)ncart(LI) * ncart(LJ));
+    if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
+    static bool opted_in = false;
+    if (lds > 64 * 1024 && !opted_in) {
+        const hipError_t e = hipFuncSetAttribute((const void *)&jk_k1_row<LI, LJ, LK, LL, R>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, ROW_LDS_MAX);
+        if (e != hipSuccess) return e;
+        opted_in = true;
+    }
+    hipLaunchKernelGGL((jk_k1_row<LI, LJ, LK, LL, R>), dim3(a.nrow), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int LI, int LJ, int LK, int LL, typename R>
+static hipError_t launch_row2(const JkArgs &a, hipStream_t s) {
+    if (a.nrow <= 0) return hipSuccess;
+    using L = K2RowLds<LI, LJ, LK, LL>;
+    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
+    const size_t lds = L::template fixed<R>() + (size_t)a.nset * L::per_set(ncols);
+    if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
+    static bool opted_in = false;
+    if (lds > 64 * 1024 && !opted_in) {
+        const hipError_t e = hipFuncSetAttribute((const void *)&jk_k2_row<LI, LJ, LK, LL, R>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, ROW_LDS_MAX);
+        if (e != hipSuccess) return e;
+        opted_in = true;
+    }
+    hipLaunchKernelGGL((jk_k2_row<LI, LJ, LK, LL, R>), dim3(a.nrow), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
 static hipError_t launch_k2(const JkArgs &a, hipStream_t s) {
     constexpr int QW = k2_qw(LI, LJ, LK, LL);
@@ -42,11 +78,17 @@ static void reg_one() {
             e.tiles[0][0] = &launch_k1<LI, LJ, LK, LL, double, MODE_JK>;
             e.tiles[0][1] = &launch_k1<LI, LJ, LK, LL, float, MODE_JK>;
             e.list64[0] = &launch_k1<LI, LJ, LK, LL, double, MODE_LIST>;
+            e.row[0][0] = &launch_row<LI, LJ, LK, LL, double>;
+            e.row[0][1] = &launch_row<LI, LJ, LK, LL, float>;
         }
         if constexpr (has_family2(LI, LJ, LK, LL)) {
             e.tiles[1][0] = &launch_k2<LI, LJ, LK, LL, double, MODE_JK>;
             e.tiles[1][1] = &launch_k2<LI, LJ, LK, LL, float, MODE_JK>;
             e.list64[1] = &launch_k2<LI, LJ, LK, LL, double, MODE_LIST>;
+            e.row[1][0] = &launch_row2<LI, LJ, LK, LL, double>;
+            e.row[1][1] = &launch_row2<LI, LJ, LK, LL, float>;
+            e.row_fixed[1][0] = K2RowLds<LI, LJ, LK, LL>::template fixed<double>();
+            e.row_fixed[1][1] = K2RowLds<LI, LJ, LK, LL>::template fixed<float>();
         }
         if constexpr (default_family(LI, LJ, LK, LL) == 1) {
             e.ex64 = &launch_k1<LI, LJ, LK, LL, double, MODE_EXPORT>;

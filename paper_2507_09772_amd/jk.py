@@ -41,8 +41,8 @@ class Stats(ctypes.Structure):
 class ClassTiming(ctypes.Structure):
     _fields_ = [("li", ctypes.c_int32), ("lj", ctypes.c_int32), ("lk", ctypes.c_int32), ("ll", ctypes.c_int32),
                 ("npb", ctypes.c_int32), ("npk", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("launches", ctypes.c_int32), ("nquartets", ctypes.c_int64), ("model_flops", ctypes.c_double),
-                ("ms", ctypes.c_double)]
+                ("launches", ctypes.c_int32), ("family", ctypes.c_int32), ("kind", ctypes.c_int32),
+                ("nquartets", ctypes.c_int64), ("model_flops", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -75,6 +75,7 @@ def lib():
         L.jk_tune_set.argtypes = [i32, i32, i32, i32, i32, i32]
         L.jk_tune_get.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.jk_tune_load.argtypes = [ctypes.c_char_p]
+        L.jk_tune_set_row.argtypes = [i32, i32, i32, i32, i32, i32]
         L.jk_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -204,6 +205,11 @@ def build(mol, D, cutoff=1e-13, precision="fp64", stream=None):
 def tune_set(li, lj, lk, ll, precision, family):
     """Kernel family (1, 2; 0 = default) for one canonical class."""
     _check(lib().jk_tune_set(li, lj, lk, ll, PRECISION[precision], family))
+
+
+def tune_set_row(li, lj, lk, ll, precision, row):
+    """Row mode for one canonical class: 0 default (allowed), 1 allowed, 2 off."""
+    _check(lib().jk_tune_set_row(li, lj, lk, ll, PRECISION[precision], row))
 
 
 def tune_get(li, lj, lk, ll, precision):

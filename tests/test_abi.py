@@ -85,3 +85,24 @@ def test_rys_eval_validation(jkmod):
         jkmod.rys_eval(3, [-1.0])
     with pytest.raises(jkmod.JKError):
         jkmod.rys_eval(10, [1.0])
+
+
+def test_shipped_tuning_table_is_applied(jkmod):
+    """Every entry of the shipped per-device table reaches the library (the
+    table is read after the kernel classes have registered)."""
+    path = os.path.join(ROOT, "paper_2507_09772_amd", "tune_gfx950.txt")
+    rows = [list(map(int, l.split())) for l in open(path) if l.strip() and not l.startswith("#")]
+    assert rows
+    for r in rows:
+        li, lj, lk, ll, pr, fam = r[:6]
+        got, avail = jkmod.tune_get(li, lj, lk, ll, "fp32" if pr == 2 else "fp64")
+        assert got == fam and avail & fam, r
+
+
+def test_tuning_validation(jkmod):
+    with pytest.raises(jkmod.JKError):
+        jkmod.tune_set(0, 1, 0, 0, "fp64", 1)   # not canonical
+    with pytest.raises(jkmod.JKError):
+        jkmod.tune_set(0, 0, 0, 0, "fp64", 2)   # (ss|ss) has no family 2
+    f, m = jkmod.tune_get(3, 3, 3, 3, "fp64")
+    assert f == 2 and m == 2

@@ -138,7 +138,8 @@ def test_jk_c0(jkmod, torch_cuda):
     assert np.abs(J2 - J).max() <= 1e-13 and np.abs(K2 - K).max() <= 1e-13
 
 
-@pytest.mark.parametrize("basis,nw,nset,cut", [("B", 2, 2, 1e-13), ("A", 5, 1, 1e-10), ("B", 3, 3, 1e-13), ("A", 1, 1, 0.0)])
+@pytest.mark.parametrize("basis,nw,nset,cut", [("B", 2, 2, 1e-13), ("A", 5, 1, 1e-10), ("B", 3, 3, 1e-13), ("A", 1, 1, 0.0),
+                                               ("A", 8, 1, 1e-13), ("B", 6, 2, 1e-13)])
 def test_jk_small(jkmod, torch_cuda, basis, nw, nset, cut):
     wl = synth.small_workload(nw, basis, seed=40 + nw, nset=nset)
     wl.cutoff = cut
@@ -170,9 +171,9 @@ def test_flags_and_accumulate(jkmod, torch_cuda):
 # ---------------------------------------------------------------------------
 # mixed precision
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("basis", ["A", "B"])
-def test_mixed_small(jkmod, torch_cuda, basis):
-    wl = synth.small_workload(4, basis, seed=77)
+@pytest.mark.parametrize("basis,nw", [("A", 4), ("B", 4), ("A", 8)])
+def test_mixed_small(jkmod, torch_cuda, basis, nw):
+    wl = synth.small_workload(nw, basis, seed=77)
     say("mixed", basis)
     J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
     ej0, ek0 = o.energies(wl.D, J0, K0)
