@@ -32,6 +32,8 @@ WORKLOAD_TEXT = {
     "c1": "64 waters 4x4x4 lattice, basis A (6-31G*-shaped, Cartesian), 1216 AOs, 1 density, cutoff 1e-13",
     "c2": "32 waters, basis B (TZ2P-shaped, spherical, up to f), 1376 AOs, 1 density, cutoff 1e-13",
 }
+BATCH_TEXT = ("256 molecules of 1-8 waters, half basis A (Cartesian), half basis B (spherical), "
+              "4 densities each, cutoff 1e-13")
 
 
 def log(*a):
@@ -107,6 +109,52 @@ def cpu_baseline(wl, target_s: float):
                       f"({full_s:.0f} s per build)"}
 
 
+def bench_batch(args, torch, jk, synth):
+    """Batched builds over the 256-molecule set: one graph replay per step
+    against the same molecules built one jk_execute at a time."""
+    import numpy as np
+    wls = synth.batch_workload()
+    t0 = time.perf_counter()
+    plans = [jk.Plan(w.mol, w.cutoff) for w in wls]
+    t_plan = time.perf_counter() - t0
+    Ds = [torch.from_numpy(w.D).cuda() for w in wls]
+    Js = [torch.empty_like(D) for D in Ds]
+    Ks = [torch.empty_like(D) for D in Ds]
+    nset = Ds[0].shape[0]
+    nq = sum(p.stats().nquartets for p in plans)
+    res = {"config": BATCH_TEXT, "nmol": len(wls), "nset": nset, "plan_seconds": t_plan, "nquartets": nq}
+    for precision in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+        b = jk.Batch(plans, nset=nset, precision=precision, mix_threshold=args.mix_threshold)
+        for _ in range(max(args.warmup, 1)):
+            b.execute(Ds, Js, Ks)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.execute(Ds, Js, Ks)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        e = [2.0 * float(np.sum(w.D * J.cpu().numpy())) for w, J in zip(wls, Js)]
+        # the same molecules one jk_execute each
+        for p, D, J, K in zip(plans, Ds, Js, Ks):
+            p.execute(D, J, K, precision=precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for p, D, J, K in zip(plans, Ds, Js, Ks):
+                p.execute(D, J, K, precision=precision)
+        torch.cuda.synchronize()
+        dts = (time.perf_counter() - t0) / args.steps
+        e1 = [2.0 * float(np.sum(w.D * J.cpu().numpy())) for w, J in zip(wls, Js)]
+        res[precision] = {"ms_per_step": dt * 1e3, "molecule_builds_per_s": len(wls) / dt,
+                          "density_builds_per_s": len(wls) * nset / dt, "quartets_per_s": nq / dt,
+                          "one_by_one_ms": dts * 1e3, "speedup_vs_one_by_one": dts / dt,
+                          "max_dE_J_vs_one_by_one": float(np.abs(np.subtract(e, e1)).max())}
+        log(f"batch {precision}: {dt * 1e3:.2f} ms/step ({len(wls) / dt:.0f} molecule builds/s), one by one "
+            f"{dts * 1e3:.2f} ms")
+        b.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +163,7 @@ def main():
     ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-molecule batched builds")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mix-threshold", type=float, default=1e-4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -197,6 +246,8 @@ def main():
                         "max_dJ_vs_fp64_gpu": float(np.abs(Jm - J64).max()),
                         "max_dK_vs_fp64_gpu": float(np.abs(Km - K64).max()),
                         "threshold": args.mix_threshold}
+    if not args.no_batch:
+        out["batch"] = bench_batch(args, torch, jk, synth)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

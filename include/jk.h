@@ -129,12 +129,23 @@ int jk_build(const jk_basis *basis, const double *D, int32_t nset, double cutoff
              double *J, double *K, void *stream);
 
 /*
- * Batched builds over many plans (molecules): all class work of all
- * molecules runs from one persistent kernel over a global work queue, and
- * the whole build is recorded once into a hipGraph and replayed.
- * nset densities per molecule.  D[m], J[m], K[m]: device pointers for
- * molecule m, recorded at the first jk_batch_execute; later calls must pass
- * the same pointers (JK_EINVAL otherwise).  Plans must outlive the batch.
+ * Batched builds over many plans (molecules), the same two-index
+ * contraction (Section 2, eq. jk) per molecule.  Per angular class and kernel family
+ * one persistent kernel walks a global queue of the tiles of every molecule
+ * (heaviest molecule first); transforms, clearing and finalisation are
+ * batched kernels over all molecules; the whole build is recorded into a
+ * hipGraph at the first jk_batch_execute and replayed on later calls.
+ *   plans[nmol]: plans created on the current device; they must outlive the
+ *                batch (the batch reads their device arrays).
+ *   nset:        densities per molecule; precision / mix_threshold as in
+ *                jk_execute (J and K are always built and overwritten).
+ *   D[m], J[m], K[m]: device FP64 [nset][nao_m][nao_m] of molecule m; D[m]
+ *                symmetric.  Pointers may change between calls (a small
+ *                host-to-device update on the stream precedes the replay).
+ * Scratch (Cartesian D, J', K', lists) is owned by the batch and shared by
+ * its calls: calls on one batch must be ordered (same stream, or the caller
+ * synchronises); concurrent calls race.  Errors: JK_EINVAL for NULL or
+ * mismatched arguments, JK_ENOMEM, JK_EDEVICE.
  */
 int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset, int32_t precision,
                     double mix_threshold, jk_batch **out);

@@ -1,14 +1,330 @@
-// jk_batch.hip -- batched many-molecule builds (placeholder until the
-// persistent queue kernel lands).
+// jk_batch.hip -- batched J/K builds over many molecules (jk_batch_* in
+// include/jk.h).
+//
+// Every molecule keeps its own plan (pairs, sorted ket lists, tiles).  The
+// batch gathers, per angular class and kernel family, the class tasks of all
+// molecules into one descriptor array; one launch per group covers the
+// tiles of all its descriptors, heaviest molecule first.  The
+// basis transforms, clearing and finalisation run as batched kernels with
+// one grid row per molecule.  The whole sequence is recorded once into a
+// hipGraph and replayed on every call.
 #include <hip/hip_runtime.h>
 
-#include "../../include/jk.h"
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <tuple>
+#include <vector>
 
-extern "C" int jk_batch_create(jk_plan *const *, int32_t, int32_t, int32_t, double, jk_batch **out) {
-    if (out) *out = nullptr;
-    return JK_EUNSUPPORTED;
+#include "jk_internal.h"
+
+namespace {
+
+// Per-molecule view for the batched helper kernels (device copy).
+struct MolDesc {
+    AoMaps maps;
+    const double *D;         // caller's density [nset][nao][nao]
+    double *J, *K;           // caller's outputs
+    double *Dc, *Jc, *Kc;    // batch scratch [nset][naoc][naoc]
+    float *dmax;             // [ns][ns]
+    int32_t nao, naoc, ns, sph;
+};
+
+// Dc = Cartesian density (transformed or copied); Jc = Kc = 0.
+__global__ void kb_prepare(const MolDesc *mols, int nset) {
+    const MolDesc &m = mols[blockIdx.y];
+    const int64_t tot = (int64_t)nset * m.naoc * m.naoc;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        m.Dc[t] = m.sph ? sph_to_cart_elem(m.maps, m.D, m.nao, m.naoc, t) : m.D[t];
+        m.Jc[t] = 0.0;
+        m.Kc[t] = 0.0;
+    }
 }
-extern "C" int jk_batch_execute(jk_batch *, const double *const *, double *const *, double *const *, void *) {
-    return JK_EUNSUPPORTED;
+
+__global__ void kb_dmax(const MolDesc *mols, int nset) {
+    const MolDesc &m = mols[blockIdx.y];
+    const int tot = m.ns * m.ns;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += gridDim.x * blockDim.x)
+        m.dmax[t] = dmax_elem(m.Dc, m.maps.aoc, m.maps.l, m.ns, m.naoc, nset, t);
 }
-extern "C" void jk_batch_destroy(jk_batch *) {}
+
+__global__ void kb_finalize(const MolDesc *mols, int nset) {
+    const MolDesc &m = mols[blockIdx.y];
+    const int64_t tot = (int64_t)nset * m.nao * m.nao;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        m.J[t] = finalize_elem(m.maps, m.Jc, m.nao, m.naoc, m.sph, t);
+        m.K[t] = finalize_elem(m.maps, m.Kc, m.nao, m.naoc, m.sph, t);
+    }
+}
+
+__global__ void kb_zero_i32(int32_t *p, int n) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0;
+}
+
+// One launch: the descriptors [first, first + count) of one (class, family)
+// group.
+struct Group {
+    int cid, fam, fam64;
+    int first, count;
+    int total_tiles;
+    int64_t list_cap;  // mixed: summed list capacity of the descriptors
+    double work;       // model FLOPs of the group, for launch order
+};
+
+}  // namespace
+
+struct jk_batch {
+    std::vector<jk_plan *> plans;
+    int nmol = 0, nset = 0, precision = 0, device = 0;
+    double thr = 0.0;
+    std::vector<MolDesc> hmol;
+    MolDesc *d_mol = nullptr;
+    std::vector<BatchDesc> hdesc;
+    BatchDesc *d_desc = nullptr;
+    std::vector<Group> groups;
+    int32_t *d_ctr = nullptr;  // mixed split: list counts per (molecule, class)
+    int nctr = 0;
+    int64_t max_elems = 0;      // largest nset * naoc^2 over the molecules
+    int max_ns2 = 0;
+    std::vector<void *> allocs;
+    MolDesc *h_stage = nullptr;  // pinned staging for pointer updates
+    hipEvent_t stage_ev = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    template <typename T>
+    int alloc(T **p, size_t n) {
+        if (n == 0) n = 1;
+        const hipError_t e = hipMalloc((void **)p, sizeof(T) * n);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? JK_ENOMEM : JK_EDEVICE, "hipMalloc(%zu): %s", sizeof(T) * n,
+                        hipGetErrorString(e));
+        allocs.push_back(*p);
+        return 0;
+    }
+    ~jk_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (stage_ev) (void)hipEventDestroy(stage_ev);
+        if (h_stage) (void)hipHostFree(h_stage);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+static int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024)); }
+
+// Records the whole batch build on b->cap.
+static int record(jk_batch *b) {
+    const int nm = b->nmol;
+    hipStream_t s = b->cap;
+    hipLaunchKernelGGL(kb_zero_i32, dim3(grid_rows(b->nctr)), dim3(256), 0, s, b->d_ctr, b->nctr);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(kb_prepare, dim3(grid_rows(b->max_elems), nm), dim3(256), 0, s, b->d_mol, b->nset);
+    HIPCHK(hipGetLastError());
+    if (b->precision == JK_MIXED) {
+        hipLaunchKernelGGL(kb_dmax, dim3(grid_rows(b->max_ns2), nm), dim3(256), 0, s, b->d_mol, b->nset);
+        HIPCHK(hipGetLastError());
+    }
+    const int pr = b->precision == JK_FP64 ? 0 : 1;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const Group &g = b->groups[gi];
+        const ClassEntry &e = g_classes[g.cid];
+        HIPCHK(e.batch[g.fam - 1][pr](b->d_desc + g.first, g.count, g.total_tiles, s));
+        if (b->precision == JK_MIXED) HIPCHK(e.batch_list[g.fam64 - 1](b->d_desc + g.first, g.count, g.list_cap, s));
+    }
+    hipLaunchKernelGGL(kb_finalize, dim3(grid_rows(b->max_elems), nm), dim3(256), 0, s, b->d_mol, b->nset);
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset, int32_t precision,
+                               double mix_threshold, jk_batch **out) {
+    if (!out) return fail(JK_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plans || nmol < 1 || nmol > 65535) return fail(JK_EINVAL, "need 1 <= nmol <= 65535 plans");
+    if (nset < 1) return fail(JK_EINVAL, "nset must be >= 1");
+    if (precision != JK_FP64 && precision != JK_MIXED && precision != JK_FP32)
+        return fail(JK_EINVAL, "bad precision %d", precision);
+    if (precision == JK_MIXED && !(std::isfinite(mix_threshold) && mix_threshold >= 0.0))
+        return fail(JK_EINVAL, "mix_threshold must be finite and >= 0");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    for (int m = 0; m < nmol; ++m) {
+        if (!plans[m]) return fail(JK_EINVAL, "plans[%d] is NULL", m);
+        if (plans[m]->device != dev) return fail(JK_EINVAL, "plans[%d] lives on device %d, current is %d", m, plans[m]->device, dev);
+    }
+    std::unique_ptr<jk_batch> b(new jk_batch);
+    b->plans.assign(plans, plans + nmol);
+    b->nmol = nmol;
+    b->nset = nset;
+    b->precision = precision;
+    b->thr = mix_threshold;
+    b->device = dev;
+    int rc;
+
+    // per-molecule scratch, one allocation each kind
+    std::vector<int64_t> eoff(nmol + 1, 0), soff(nmol + 1, 0), loff(nmol + 1, 0), coff(nmol + 1, 0);
+    for (int m = 0; m < nmol; ++m) {
+        const jk_plan *P = plans[m];
+        const int64_t e = (int64_t)nset * P->naoc * P->naoc;
+        eoff[m + 1] = eoff[m] + e;
+        soff[m + 1] = soff[m] + (int64_t)P->ns * P->ns;
+        loff[m + 1] = loff[m] + 2 * std::max<int64_t>(P->stats.nquartets, 1);
+        coff[m + 1] = coff[m] + (int64_t)P->cls.size();
+        b->max_elems = std::max(b->max_elems, e);
+        b->max_ns2 = std::max(b->max_ns2, P->ns * P->ns);
+    }
+    double *Dc, *Jc, *Kc;
+    float *dmax = nullptr;
+    int32_t *list = nullptr;
+    if ((rc = b->alloc(&Dc, eoff[nmol])) || (rc = b->alloc(&Jc, eoff[nmol])) || (rc = b->alloc(&Kc, eoff[nmol])))
+        return rc;
+    if (precision == JK_MIXED && ((rc = b->alloc(&dmax, soff[nmol])) || (rc = b->alloc(&list, loff[nmol])))) return rc;
+
+    // descriptors grouped by (class, family); heavy molecules first
+    const int pr = precision == JK_FP64 ? 0 : 1;
+    std::map<std::tuple<int, int, int>, std::vector<std::pair<double, BatchDesc>>> byg;
+    b->hmol.resize(nmol);
+    for (int m = 0; m < nmol; ++m) {
+        const jk_plan *P = plans[m];
+        MolDesc &md = b->hmol[m];
+        md.maps = P->maps;
+        md.D = nullptr;
+        md.J = md.K = nullptr;
+        md.Dc = Dc + eoff[m];
+        md.Jc = Jc + eoff[m];
+        md.Kc = Kc + eoff[m];
+        md.dmax = dmax ? dmax + soff[m] : nullptr;
+        md.nao = P->nao;
+        md.naoc = P->naoc;
+        md.ns = P->ns;
+        md.sph = P->sph;
+        for (size_t ci = 0; ci < P->cls.size(); ++ci) {
+            const ClassTask &c = P->cls[ci];
+            const int f = c.fam[pr];
+            if (c.ntiles[f - 1] <= 0) continue;
+            BatchDesc d{};
+            JkArgs &a = d.a;
+            a.pairs = P->d_pairs;
+            a.pp = P->d_pp;
+            a.bra_list = c.d_bra;
+            a.bra_cnt = c.d_cnt;
+            a.nbra = c.nbra;
+            a.tile_off = c.d_tile[f - 1];
+            a.ntiles = c.ntiles[f - 1];
+            a.ket_list = c.d_ket;
+            a.same = c.same;
+            a.npb = c.npb;
+            a.npk = c.npk;
+            a.nq = (int32_t)c.nq;
+            a.list = list ? list + loff[m] + 2 * c.list_off : nullptr;
+            a.list_count = nullptr;  // set below, after the counter layout is known
+            a.tpos = P->d_tpos;
+            a.aoc = P->maps.aoc;
+            a.D = md.Dc;
+            a.J = md.Jc;
+            a.K = md.Kc;
+            a.mstride = (int64_t)P->naoc * P->naoc;
+            a.nao = P->naoc;
+            a.nset = nset;
+            a.do_j = 1;
+            a.do_k = 1;
+            a.dmax = md.dmax;
+            a.nshell = P->ns;
+            a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
+            a.mix_thr = mix_threshold;
+            a.tab = P->tab;
+            d.pad[0] = (int32_t)(coff[m] + (int64_t)ci);  // list counter slot (host only)
+            const ClassEntry &e = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
+            if (!e.batch[f - 1][pr] || (precision == JK_MIXED && !e.batch_list[c.fam[0] - 1]))
+                return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has no batched kernel", c.li, c.lj, c.lk, c.ll);
+            byg[{class_id(c.li, c.lj, c.lk, c.ll), f, c.fam[0]}].push_back({c.flops, d});
+        }
+    }
+    for (auto &kv : byg) {
+        auto &v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+        Group g{};
+        g.cid = std::get<0>(kv.first);
+        g.fam = std::get<1>(kv.first);
+        g.fam64 = std::get<2>(kv.first);
+        g.first = (int)b->hdesc.size();
+        g.count = (int)v.size();
+        int64_t tiles = 0;
+        for (auto &x : v) {
+            x.second.tile_base = (int32_t)tiles;
+            tiles += x.second.a.ntiles;
+            g.list_cap += x.second.a.nq;
+            g.work += x.first;
+            b->hdesc.push_back(x.second);
+        }
+        if (tiles > INT32_MAX) return fail(JK_EINVAL, "too many tiles in one class group");
+        g.total_tiles = (int)tiles;
+        b->groups.push_back(g);
+    }
+    std::stable_sort(b->groups.begin(), b->groups.end(), [](const Group &x, const Group &y) { return x.work > y.work; });
+    // one list count per (molecule, class)
+    b->nctr = (int)coff[nmol];
+    if ((rc = b->alloc(&b->d_ctr, b->nctr))) return rc;
+    for (BatchDesc &d : b->hdesc) {
+        d.a.list_count = precision == JK_MIXED ? b->d_ctr + d.pad[0] : nullptr;
+        d.pad[0] = 0;
+    }
+    if ((rc = b->alloc(&b->d_desc, b->hdesc.size())) || (rc = b->alloc(&b->d_mol, nmol))) return rc;
+    if (!b->hdesc.empty())
+        HIPCHK(hipMemcpy(b->d_desc, b->hdesc.data(), sizeof(BatchDesc) * b->hdesc.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipHostMalloc((void **)&b->h_stage, sizeof(MolDesc) * nmol, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    *out = b.release();
+    return JK_OK;
+}
+
+extern "C" int jk_batch_execute(jk_batch *b, const double *const *D, double *const *J, double *const *K, void *stream) {
+    if (!b) return fail(JK_EINVAL, "batch is NULL");
+    if (!D || !J || !K) return fail(JK_EINVAL, "D, J and K pointer arrays must be non-NULL");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != b->device) return fail(JK_EINVAL, "batch was created on device %d, current device is %d", b->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    bool changed = false;
+    for (int m = 0; m < b->nmol; ++m) {
+        if (!D[m] || !J[m] || !K[m]) return fail(JK_EINVAL, "molecule %d: NULL D, J or K", m);
+        MolDesc &md = b->hmol[m];
+        if (md.D != D[m] || md.J != J[m] || md.K != K[m]) {
+            md.D = D[m];
+            md.J = J[m];
+            md.K = K[m];
+            changed = true;
+        }
+    }
+    if (changed) {
+        // the previous upload from the staging buffer must have completed
+        HIPCHK(hipEventSynchronize(b->stage_ev));
+        std::memcpy(b->h_stage, b->hmol.data(), sizeof(MolDesc) * b->nmol);
+        HIPCHK(hipMemcpyAsync(b->d_mol, b->h_stage, sizeof(MolDesc) * b->nmol, hipMemcpyHostToDevice, s));
+        HIPCHK(hipEventRecord(b->stage_ev, s));
+    }
+    if (!b->exec) {
+        HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = record(b);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        HIPCHK(e);
+        b->graph = g;
+        HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(b->exec, s));
+    return JK_OK;
+}
+
+extern "C" void jk_batch_destroy(jk_batch *b) { delete b; }

@@ -547,13 +547,11 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
     }
 }
 
-// Tiles: one wave per tile of 64 kets of one bra.
-template <int LI, int LJ, int LK, int LL, typename R, int MODE>
-__global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
+// One tile (64 kets of one bra) for one wave.
+template <int LI, int LJ, int LK, int LL, typename R>
+__device__ __forceinline__ void k1_tile(const JkArgs &a, int wave) {
     const int lane = lane_index();
-    if constexpr (MODE == MODE_JK) {
-        const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-        if (wave >= a.ntiles) return;
+    {
         const int i = tile_bra(a.tile_off, a.nbra, wave);
         const int j = (wave - a.tile_off[i]) * 64 + lane;
         const int cnt = a.bra_cnt[i];
@@ -569,6 +567,17 @@ __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
             valid = valid && !hi;
         }
         k1_body<LI, LJ, LK, LL, R, MODE_JK>(a, bra, ket, valid, wq, 0);
+    }
+}
+
+// Tiles: one wave per tile of 64 kets of one bra.
+template <int LI, int LJ, int LK, int LL, typename R, int MODE>
+__global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
+    const int lane = lane_index();
+    if constexpr (MODE == MODE_JK) {
+        const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+        if (wave >= a.ntiles) return;
+        k1_tile<LI, LJ, LK, LL, R>(a, wave);
     } else if constexpr (MODE == MODE_EXPORT) {
         const int g = blockIdx.x * 256 + threadIdx.x;
         const bool valid = g < a.nq;
@@ -997,6 +1006,30 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
     }
 }
 
+// One tile (QW kets of one bra) for the one-wave workgroup, expanded in
+// place in each kernel.  As a helper function taking the LDS arrays as
+// pointers, the compiler kept the large FP64 classes' accumulators in
+// scratch (four times the private memory of the in-place form) and the
+// (ff|ff) kernel returned wrong values.
+#define JK_K2_TILE(a, wave)                                                     \
+    do {                                                                        \
+        const int i_ = tile_bra((a).tile_off, (a).nbra, (wave));                \
+        const int j_ = ((wave) - (a).tile_off[i_]) * QW + qq;                   \
+        const int cnt_ = (a).bra_cnt[i_];                                       \
+        bool valid_ = lane_used && j_ < cnt_;                                   \
+        const int bra_ = (a).bra_list[i_];                                      \
+        const int ket_ = (a).ket_list[j_ < cnt_ ? j_ : cnt_ - 1];               \
+        const PairRec &B_ = (a).pairs[bra_];                                    \
+        const PairRec &K_ = (a).pairs[ket_];                                    \
+        const double wq_ = pair_weight(bra_, ket_, B_, K_);                     \
+        if ((a).sel == SEL_LOW) {                                               \
+            const bool hi_ = valid_ && above_threshold((a), B_, K_);            \
+            list_append((a), hi_ && sl == 0, bra_, ket_);                       \
+            valid_ = valid_ && !hi_;                                            \
+        }                                                                       \
+        k2_body<LI, LJ, LK, LL, R, MODE_JK>((a), tabs, dig, bra_, ket_, valid_, wq_, 0); \
+    } while (0)
+
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
 __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
     using F = K2Cfg<LI, LJ, LK, LL>;
@@ -1009,22 +1042,7 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
     const bool lane_used = q < QW;
     const int qq = lane_used ? q : 0;
     if constexpr (MODE == MODE_JK) {
-        const int wave = blockIdx.x;
-        const int i = tile_bra(a.tile_off, a.nbra, wave);
-        const int j = (wave - a.tile_off[i]) * QW + qq;
-        const int cnt = a.bra_cnt[i];
-        bool valid = lane_used && j < cnt;
-        const int bra = a.bra_list[i];
-        const int ket = a.ket_list[j < cnt ? j : cnt - 1];
-        const PairRec &B = a.pairs[bra];
-        const PairRec &Kt = a.pairs[ket];
-        const double wq = pair_weight(bra, ket, B, Kt);
-        if (a.sel == SEL_LOW) {
-            const bool hi = valid && above_threshold(a, B, Kt);
-            list_append(a, hi && sl == 0, bra, ket);
-            valid = valid && !hi;
-        }
-        k2_body<LI, LJ, LK, LL, R, MODE_JK>(a, tabs, dig, bra, ket, valid, wq, 0);
+        JK_K2_TILE(a, (int)blockIdx.x);
     } else if constexpr (MODE == MODE_EXPORT) {
         const int gq = blockIdx.x * QW + qq;
         const bool valid = lane_used && gq < a.nq;
@@ -1115,6 +1133,99 @@ __global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
             if (c < a.ncolK) col = a.aoc[a.tshK[c / ncart(LK)]] + c % ncart(LK);
             else col = a.aoc[a.tshL[(c - a.ncolK) / ncart(LL)]] + (c - a.ncolK) % ncart(LL);
             atomic_add_f64(&Km[row * n + col], v);
+        }
+    }
+}
+
+// ===========================================================================
+// Batched builds: one launch per (class, family) covers the tiles of every
+// molecule of the batch.  Global tile g belongs to the descriptor m with
+// tile_base[m] <= g < tile_base[m + 1]; each descriptor holds the JkArgs of
+// one (molecule, class task), heaviest first, so the dispatcher hands out
+// the long tiles early.
+// ===========================================================================
+struct BatchDesc {
+    JkArgs a;
+    int32_t tile_base;
+    int32_t pad[3];
+};
+
+__device__ __forceinline__ int batch_desc(const BatchDesc *__restrict__ d, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile_base <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int LI, int LJ, int LK, int LL, typename R>
+__global__ void __launch_bounds__(256) jk_k1_batch(const BatchDesc *__restrict__ descs, int ndesc, int total) {
+    const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (g >= total) return;
+    const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
+    const JkArgs a = descs[m].a;
+    k1_tile<LI, LJ, LK, LL, R>(a, g - descs[m].tile_base);
+}
+
+template <int LI, int LJ, int LK, int LL, typename R>
+__global__ void __launch_bounds__(64) jk_k2_batch(const BatchDesc *__restrict__ descs, int ndesc, int total) {
+    using F = K2Cfg<LI, LJ, LK, LL>;
+    constexpr int QW = F::QW, LPQ = F::LPQ;
+    __shared__ R tabs[QW * F::TAB];
+    __shared__ double dig[QW * F::DIG];
+    const int lane = threadIdx.x;
+    const int q = QW > 1 ? lane / LPQ : 0;
+    const int sl = QW > 1 ? lane % LPQ : lane;
+    const bool lane_used = q < QW;
+    const int qq = lane_used ? q : 0;
+    const int g = blockIdx.x;
+    const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
+    const JkArgs a = descs[m].a;
+    JK_K2_TILE(a, g - descs[m].tile_base);
+}
+
+// FP64 pass of the mixed split over every descriptor's appended list.
+template <int LI, int LJ, int LK, int LL>
+__global__ void __launch_bounds__(256) jk_k1_batch_list(const BatchDesc *__restrict__ descs, int ndesc) {
+    const int lane = lane_index();
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwave = gridDim.x * 4;
+    for (int m = 0; m < ndesc; ++m) {
+        const JkArgs &a = descs[m].a;
+        const int cnt = min(*a.list_count, a.nq);
+        for (int g0 = wave * 64; g0 < cnt; g0 += nwave * 64) {
+            const int g = g0 + lane;
+            const bool valid = g < cnt;
+            const int gg = valid ? g : cnt - 1;
+            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
+            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
+            k1_body<LI, LJ, LK, LL, double, MODE_LIST>(a, bra, ket, valid, wq, 0);
+        }
+    }
+}
+
+template <int LI, int LJ, int LK, int LL>
+__global__ void __launch_bounds__(64) jk_k2_batch_list(const BatchDesc *__restrict__ descs, int ndesc) {
+    using F = K2Cfg<LI, LJ, LK, LL>;
+    constexpr int QW = F::QW, LPQ = F::LPQ;
+    __shared__ double tabs[QW * F::TAB];
+    __shared__ double dig[QW * F::DIG];
+    const int lane = lane_index();
+    const int q = QW > 1 ? lane / LPQ : 0;
+    const bool lane_used = q < QW;
+    const int qq = lane_used ? q : 0;
+    for (int m = 0; m < ndesc; ++m) {
+        const JkArgs &a = descs[m].a;
+        const int cnt = min(*a.list_count, a.nq);
+        for (int b0 = blockIdx.x * QW; b0 < cnt; b0 += gridDim.x * QW) {
+            const int gq = b0 + qq;
+            const bool valid = lane_used && gq < cnt;
+            const int gg = gq < cnt ? gq : cnt - 1;
+            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
+            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
+            wave_sync();
+            k2_body<LI, LJ, LK, LL, double, MODE_LIST>(a, tabs, dig, bra, ket, valid, wq, 0);
         }
     }
 }

@@ -9,6 +9,9 @@ namespace jk {
 constexpr int LMAX_BUILT = 3;  // classes instantiated up to (ff|ff)
 
 using Launcher = hipError_t (*)(const JkArgs &, hipStream_t);
+// Batched builds: the tiles of many descriptors (molecules) in one launch.
+using BatchLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int total_tiles, hipStream_t);
+using BatchListLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int64_t nq_total, hipStream_t);
 
 struct ClassEntry {
     Launcher tiles[2][2];  // [family - 1][0: FP64, 1: FP32], quartets from tiles
@@ -16,6 +19,8 @@ struct ClassEntry {
     Launcher ex64, ex32;   // export (default family)
     Launcher row[2][2];    // row mode, [family - 1][0: FP64, 1: FP32]
     size_t row_fixed[2][2];  // row-mode LDS bytes besides the K rows, [family - 1][precision]
+    BatchLauncher batch[2][2];       // [family - 1][precision]
+    BatchListLauncher batch_list[2]; // [family - 1], FP64 list pass of the mixed split
 };
 
 // LDS bytes of one row-mode workgroup: the fixed part plus nset copies of

@@ -69,6 +69,38 @@ static hipError_t launch_k2(const JkArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Batched tiles: one wave (family 1) or one workgroup (family 2) per tile.
+template <int LI, int LJ, int LK, int LL, typename R>
+static hipError_t launch_k1_batch(const BatchDesc *d, int ndesc, int total, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((jk_k1_batch<LI, LJ, LK, LL, R>), dim3((total + 3) / 4), dim3(256), 0, s, d, ndesc, total);
+    return hipGetLastError();
+}
+
+template <int LI, int LJ, int LK, int LL, typename R>
+static hipError_t launch_k2_batch(const BatchDesc *d, int ndesc, int total, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL((jk_k2_batch<LI, LJ, LK, LL, R>), dim3(total), dim3(64), 0, s, d, ndesc, total);
+    return hipGetLastError();
+}
+
+template <int LI, int LJ, int LK, int LL>
+static hipError_t launch_k1_batch_list(const BatchDesc *d, int ndesc, int64_t nq, hipStream_t s) {
+    if (ndesc <= 0 || nq <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((nq + 255) / 256, 1024);
+    hipLaunchKernelGGL((jk_k1_batch_list<LI, LJ, LK, LL>), dim3(grid), dim3(256), 0, s, d, ndesc);
+    return hipGetLastError();
+}
+
+template <int LI, int LJ, int LK, int LL>
+static hipError_t launch_k2_batch_list(const BatchDesc *d, int ndesc, int64_t nq, hipStream_t s) {
+    if (ndesc <= 0 || nq <= 0) return hipSuccess;
+    constexpr int QW = k2_qw(LI, LJ, LK, LL);
+    const int grid = (int)std::min<int64_t>((nq + QW - 1) / QW, 4096);
+    hipLaunchKernelGGL((jk_k2_batch_list<LI, LJ, LK, LL>), dim3(grid), dim3(64), 0, s, d, ndesc);
+    return hipGetLastError();
+}
+
 template <int LK, int LL>
 static void reg_one() {
     constexpr int LI = JK_LI, LJ = JK_LJ;
@@ -80,6 +112,9 @@ static void reg_one() {
             e.list64[0] = &launch_k1<LI, LJ, LK, LL, double, MODE_LIST>;
             e.row[0][0] = &launch_row<LI, LJ, LK, LL, double>;
             e.row[0][1] = &launch_row<LI, LJ, LK, LL, float>;
+            e.batch[0][0] = &launch_k1_batch<LI, LJ, LK, LL, double>;
+            e.batch[0][1] = &launch_k1_batch<LI, LJ, LK, LL, float>;
+            e.batch_list[0] = &launch_k1_batch_list<LI, LJ, LK, LL>;
         }
         if constexpr (has_family2(LI, LJ, LK, LL)) {
             e.tiles[1][0] = &launch_k2<LI, LJ, LK, LL, double, MODE_JK>;
@@ -89,6 +124,9 @@ static void reg_one() {
             e.row[1][1] = &launch_row2<LI, LJ, LK, LL, float>;
             e.row_fixed[1][0] = K2RowLds<LI, LJ, LK, LL>::template fixed<double>();
             e.row_fixed[1][1] = K2RowLds<LI, LJ, LK, LL>::template fixed<float>();
+            e.batch[1][0] = &launch_k2_batch<LI, LJ, LK, LL, double>;
+            e.batch[1][1] = &launch_k2_batch<LI, LJ, LK, LL, float>;
+            e.batch_list[1] = &launch_k2_batch_list<LI, LJ, LK, LL>;
         }
         if constexpr (default_family(LI, LJ, LK, LL) == 1) {
             e.ex64 = &launch_k1<LI, LJ, LK, LL, double, MODE_EXPORT>;

@@ -189,6 +189,46 @@ class Plan:
         return out
 
 
+class Batch:
+    """jk_batch: one build over many molecules (one plan each), recorded
+    into a hipGraph at the first call and replayed afterwards."""
+
+    def __init__(self, plans, nset: int, precision="fp64", mix_threshold: float = 1e-4):
+        self.plans = list(plans)  # keeps the plans alive as long as the batch
+        self.nset = int(nset)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.h.value for p in self.plans])
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _check(lib().jk_batch_create(arr, len(self.plans), self.nset, prec, mix_threshold, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().jk_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def execute(self, Ds, Js, Ks, stream=None):
+        """Ds, Js, Ks: lists of contiguous float64 CUDA tensors
+        [nset, nao_m, nao_m], one per molecule (outputs overwritten)."""
+        import torch
+        n = len(self.plans)
+        if not (len(Ds) == len(Js) == len(Ks) == n):
+            raise ValueError(f"need {n} D, J and K tensors")
+        for P, *Ms in zip(self.plans, Ds, Js, Ks):
+            for M in Ms:
+                if (M.dtype != torch.float64 or not M.is_cuda or not M.is_contiguous()
+                        or tuple(M.shape) != (self.nset, P.nao, P.nao)):
+                    raise ValueError(f"tensors must be contiguous float64 CUDA [{self.nset}, {P.nao}, {P.nao}]")
+        ptrs = [(ctypes.c_void_p * n)(*[M.data_ptr() for M in Ms]) for Ms in (Ds, Js, Ks)]
+        _check(lib().jk_batch_execute(self.h, ptrs[0], ptrs[1], ptrs[2], _stream_handle(stream)))
+
+
 def build(mol, D, cutoff=1e-13, precision="fp64", stream=None):
     """One-shot jk_build.  D: torch float64 CUDA [nset, nao, nao]."""
     import torch

@@ -5,6 +5,10 @@ stores E_J = 2 Tr(D J) and E_K = Tr(D K) (closed-shell reading, see DESIGN),
 the number of significant unique quartets, and every 97th element of J and
 K in row-major order.  Run: python tests/golden/make_golden.py c1 c2
 (about half an hour per workload on 8 cores).
+
+c4 (256 molecules, 4 densities each) stores, per molecule, both energies
+for every density and every 2003rd element of J and K:
+python tests/golden/make_golden.py c4 (about half an hour on 8 cores).
 """
 import json
 import os
@@ -20,11 +24,30 @@ from oracle import oracle as o  # noqa: E402
 from paper_2507_09772_amd import synth  # noqa: E402
 
 STRIDE = 97
+BATCH_STRIDE = 2003
+
+
+def batch_golden():
+    mols = []
+    t0 = time.time()
+    for m, wl in enumerate(synth.batch_workload()):
+        J, K, nsig = o.jk(wl.mol, wl.D, 1e-13, mode=1)
+        ej, ek = o.energies(wl.D, J, K)
+        mols.append(dict(nao=int(wl.mol.nao), nsig=nsig, E_J=[float(x) for x in ej], E_K=[float(x) for x in ek],
+                         J=J.ravel()[::BATCH_STRIDE].tolist(), K=K.ravel()[::BATCH_STRIDE].tolist()))
+        print(m, wl.mol.nwater, wl.mol.nao, f"{time.time() - t0:.0f}s", flush=True)
+    out = dict(workload="c4", cutoff=1e-13, stride=BATCH_STRIDE, molecules=mols,
+               oracle_seconds=time.time() - t0, oracle_threads=o.num_threads())
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_jk.json"), "w") as f:
+        json.dump(out, f)
 
 
 def main(names):
     o.build_oracle(force=False)
     for name in names:
+        if name == "c4":
+            batch_golden()
+            continue
         wl = synth.workload(name)
         t0 = time.time()
         Q = o.schwarz(wl.mol)

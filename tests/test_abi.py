@@ -106,3 +106,17 @@ def test_tuning_validation(jkmod):
         jkmod.tune_set(0, 0, 0, 0, "fp64", 2)   # (ss|ss) has no family 2
     f, m = jkmod.tune_get(3, 3, 3, 3, "fp64")
     assert f == 2 and m == 2
+
+
+def test_batch_validation(jkmod):
+    L = jkmod.lib()
+    h = ctypes.c_void_p()
+    assert L.jk_batch_create(None, 1, 1, 0, 0.0, ctypes.byref(h)) == -1
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.jk_batch_create(arr, 0, 1, 0, 0.0, ctypes.byref(h)) == -1
+    assert L.jk_batch_create(arr, 1, 0, 0, 0.0, ctypes.byref(h)) == -1
+    assert L.jk_batch_create(arr, 1, 1, 7, 0.0, ctypes.byref(h)) == -1
+    assert L.jk_batch_create(arr, 1, 1, 1, float("nan"), ctypes.byref(h)) == -1
+    assert not h.value
+    assert L.jk_batch_execute(None, None, None, None, None) == -1
+    L.jk_batch_destroy(None)
