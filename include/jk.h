@@ -130,11 +130,11 @@ int jk_build(const jk_basis *basis, const double *D, int32_t nset, double cutoff
 
 /*
  * Batched builds over many plans (molecules), the same two-index
- * contraction (Section 2, eq. jk) per molecule.  Per angular class and kernel family
- * one persistent kernel walks a global queue of the tiles of every molecule
- * (heaviest molecule first); transforms, clearing and finalisation are
- * batched kernels over all molecules; the whole build is recorded into a
- * hipGraph at the first jk_batch_execute and replayed on later calls.
+ * contraction (Section 2, eq. jk) per molecule.  Per angular class and
+ * kernel family one launch covers the tiles of every molecule (heaviest
+ * molecule first); transforms, clearing and finalisation are batched
+ * kernels over all molecules; the whole build is recorded into a hipGraph
+ * at the first jk_batch_execute and replayed on later calls.
  *   plans[nmol]: plans created on the current device; they must outlive the
  *                batch (the batch reads their device arrays).
  *   nset:        densities per molecule; precision / mix_threshold as in
