@@ -493,7 +493,23 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 c.nrow = (int)rows.size();
                 c.nsbra = (int)sb.size();
                 if (c.nrow > 0 && (ce.row[0][0] || ce.row[1][0])) {
-                    if ((rc = P->put(&c.d_row, rows))) return rc;
+                    // row tasks: (list position, first ket, end ket), each long
+                    // bra cut into near-equal chunks of at most row_chunk kets
+                    for (int f = 0; f < 2; ++f) {
+                        if (!ce.row[f][0]) continue;
+                        const int ch = row_chunk(f + 1, c.li, c.lj, c.lk, c.ll);
+                        std::vector<int32_t> tasks;
+                        for (int32_t i : rows) {
+                            const int64_t n = cn[i], nch = (n + ch - 1) / ch, len = (n + nch - 1) / nch;
+                            for (int64_t j = 0; j < n; j += len) {
+                                tasks.push_back(i);
+                                tasks.push_back((int32_t)j);
+                                tasks.push_back((int32_t)std::min<int64_t>(n, j + len));
+                            }
+                        }
+                        c.nrowc[f] = (int)(tasks.size() / 3);
+                        if ((rc = P->put(&c.d_rowc[f], tasks))) return rc;
+                    }
                     if (c.nsbra > 0) {
                         if ((rc = P->put(&c.d_sbra, sb)) || (rc = P->put(&c.d_scnt, scn))) return rc;
                         for (int f = 0; f < 2; ++f) {
@@ -794,8 +810,8 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
             // long bras: one workgroup each; the short rest as tiles
             a.bra_list = c.d_bra;
             a.bra_cnt = c.d_cnt;
-            a.row_pos = c.d_row;
-            a.nrow = c.nrow;
+            a.row_pos = c.d_rowc[f - 1];
+            a.nrow = c.nrowc[f - 1];
             a.tshK = c.d_tshK;
             a.tshL = c.d_tshL;
             a.ncolK = c.ncolK;

@@ -63,6 +63,13 @@ JK_HD constexpr int k2_slots(int li, int lj, int lk, int ll) { return ncart(li) 
 JK_HD constexpr int k2_qw(int li, int lj, int lk, int ll) {
     return k2_slots(li, lj, lk, ll) >= 64 ? 1 : 64 / k2_slots(li, lj, lk, ll);
 }
+
+// Row mode: kets per workgroup task.  Long bras are cut into chunks so one
+// bra's kets spread over several workgroups (family 1 computes 256 kets
+// per pass, family 2 four waves of k2_qw quartets).
+JK_HD constexpr int row_chunk(int fam, int li, int lj, int lk, int ll) {
+    return fam == 1 ? 2048 : 256 * k2_qw(li, lj, lk, ll);
+}
 // Quartets per wave-tile of a family.
 JK_HD constexpr int quartets_per_tile(int fam, int li, int lj, int lk, int ll) {
     return fam == 1 ? 64 : k2_qw(li, lj, lk, ll);
@@ -102,7 +109,7 @@ struct JkArgs {
     // reads them back (nq is the capacity)
     int32_t *list;
     int32_t *list_count;
-    // row mode: list positions of the long bras; column segments of the ket
+    // row mode: tasks (list position, ket begin, ket end); column segments of the ket
     // shell types (shells of each type in order; tpos = index of a shell
     // within its type); segment L aliases segment K when the types match
     const int32_t *row_pos;

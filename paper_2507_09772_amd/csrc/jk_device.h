@@ -609,8 +609,8 @@ __global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NAB = C::NAB, NCD = C::NCD;
     extern __shared__ double rowmem[];
     const int tid = threadIdx.x, lane = lane_index();
-    const int i = a.row_pos[blockIdx.x];
-    const int cnt = a.bra_cnt[i];
+    const int i = a.row_pos[3 * blockIdx.x];
+    const int jbeg = a.row_pos[3 * blockIdx.x + 1], cnt = a.row_pos[3 * blockIdx.x + 2];
     const int bra = a.bra_list[i];
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
     const int segL = a.seg_same ? 0 : a.ncolK;
@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
     __syncthreads();
     const PairRec B = a.pairs[bra];
     const int n = a.nao;
-    for (int j0 = 0; j0 < cnt; j0 += 256) {
+    for (int j0 = jbeg; j0 < cnt; j0 += 256) {
         const int j = j0 + tid;
         bool valid = j < cnt;
         const int ket = a.ket_list[valid ? j : cnt - 1];
@@ -1090,8 +1090,8 @@ __global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
     double *rows = smem2;
     double *dig = rows + (size_t)per_set * a.nset + (size_t)wave * QW * F::DIG;
     R *tabs = (R *)(rows + (size_t)per_set * a.nset + 4 * QW * F::DIG) + (size_t)wave * QW * F::TAB;
-    const int i = a.row_pos[blockIdx.x];
-    const int cnt = a.bra_cnt[i];
+    const int i = a.row_pos[3 * blockIdx.x];
+    const int jbeg = a.row_pos[3 * blockIdx.x + 1], cnt = a.row_pos[3 * blockIdx.x + 2];
     const int bra = a.bra_list[i];
     for (int t = tid; t < per_set * a.nset; t += 256) rows[t] = 0.0;
     __syncthreads();
@@ -1100,7 +1100,7 @@ __global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
     const bool lane_used = q < QW;
     const int qq = lane_used ? q : 0;
     const PairRec &B = a.pairs[bra];
-    for (int j0 = wave * QW; j0 < cnt; j0 += 4 * QW) {
+    for (int j0 = jbeg + wave * QW; j0 < cnt; j0 += 4 * QW) {
         const int j = j0 + qq;
         bool valid = lane_used && j < cnt;
         const int ket = a.ket_list[j < cnt ? j : cnt - 1];

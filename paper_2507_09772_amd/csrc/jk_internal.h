@@ -116,7 +116,9 @@ struct ClassTask {
     // row mode: long bras (positions into d_bra / d_cnt) and the short rest
     int nrow = 0, nsbra = 0, nstiles[2] = {0, 0};
     int64_t nq_row = 0;  // quartets of the long bras
-    int32_t *d_row = nullptr, *d_sbra = nullptr, *d_scnt = nullptr, *d_stile[2] = {nullptr, nullptr};
+    int nrowc[2] = {0, 0};                       // row tasks per family
+    int32_t *d_rowc[2] = {nullptr, nullptr};     // (list position, ket begin, ket end) per task
+    int32_t *d_sbra = nullptr, *d_scnt = nullptr, *d_stile[2] = {nullptr, nullptr};
     int ncolK = 0, ncolL = 0, seg_same = 0;
     const int32_t *d_tshK = nullptr, *d_tshL = nullptr;
     int fam[2];          // family per precision (0 FP64, 1 FP32)
