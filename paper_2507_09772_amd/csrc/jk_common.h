@@ -55,7 +55,7 @@ struct PrimPair {
 //   1: one lane per quartet (register-resident integral block);
 //   2: a lane group per quartet, 2-D integrals staged in LDS.
 JK_HD constexpr int ncart4(int li, int lj, int lk, int ll) { return ncart(li) * ncart(lj) * ncart(lk) * ncart(ll); }
-JK_HD constexpr bool has_family1(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) <= 81; }
+JK_HD constexpr bool has_family1(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) <= 180; }
 JK_HD constexpr bool has_family2(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) >= 18; }
 JK_HD constexpr int default_family(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) <= 36 ? 1 : 2; }
 // Family 2: lanes per quartet = ncart(li) * ncart(lk) (slot = (a, c)).

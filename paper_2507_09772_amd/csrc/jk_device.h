@@ -453,16 +453,24 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                 const double w2 = valid ? 2.0 * wq : 0.0;
                 if constexpr (BRA_UNIFORM) {
                     // J_IJ: reduce over the wave's kets
-                    double mine = 0.0;
+                    // lane e holds the reduced elements e, e + 64, ...
+                    constexpr int NM = (NAB + 63) / 64;
+                    double mine[NM];
+#pragma unroll
+                    for (int m = 0; m < NM; ++m) mine[m] = 0.0;
 #pragma unroll
                     for (int ab2 = 0; ab2 < NAB; ++ab2) {
                         double s2 = 0.0;
 #pragma unroll
                         for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
                         s2 = wave_sum(s2 * w2);
-                        if (lane == ab2) mine = s2;
+                        if (lane == ab2 % 64) mine[ab2 / 64] = s2;
                     }
-                    if (lane < NAB) atomic_add_f64(&Jm[(B.aoi + lane / NJ) * n + B.aoj + lane % NJ], mine);
+#pragma unroll
+                    for (int m = 0; m < NM; ++m) {
+                        const int e = lane + 64 * m;
+                        if (e < NAB) atomic_add_f64(&Jm[(B.aoi + e / NJ) * n + B.aoj + e % NJ], mine[m]);
+                    }
                 } else if (valid) {
 #pragma unroll
                     for (int ab2 = 0; ab2 < NAB; ++ab2) {
@@ -648,16 +656,21 @@ __global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
 #pragma unroll
                     for (int l = 0; l < NL; ++l) dkl[k * NL + l] = D[(Kt.aoi + k) * n + Kt.aoj + l];
                 const double w2 = valid ? 2.0 * wq : 0.0;
-                double mine = 0.0;
+                constexpr int NM = (NAB + 63) / 64;
+                double mine[NM];
+#pragma unroll
+                for (int m = 0; m < NM; ++m) mine[m] = 0.0;
 #pragma unroll
                 for (int ab2 = 0; ab2 < NAB; ++ab2) {
                     double s2 = 0.0;
 #pragma unroll
                     for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
                     s2 = wave_sum(s2 * w2);
-                    if (lane == ab2) mine = s2;
+                    if (lane == ab2 % 64) mine[ab2 / 64] = s2;
                 }
-                if (lane < NAB) atomicAdd(&jij[lane], mine);
+#pragma unroll
+                for (int m = 0; m < NM; ++m)
+                    if (lane + 64 * m < NAB) atomicAdd(&jij[lane + 64 * m], mine[m]);
                 if (valid) {
                     double *Jm = a.J + s * a.mstride;
 #pragma unroll

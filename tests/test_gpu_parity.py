@@ -6,6 +6,7 @@ workloads; at the full config sizes the oracle computes sampled blocks of
 J and K one by one from the definition.
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -219,3 +220,39 @@ def test_full_size_sampled(jkmod, torch_cuda, name):
     assert np.abs(K[0] - K[0].T).max() <= 1e-12
     tj, tk = float(np.sum(D * J[0])), float(np.sum(D * K[0]))
     assert tj > 0 and 0 <= tk <= tj
+
+
+# ---------------------------------------------------------------------------
+# every kernel family and row setting, not only the tuned ones
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("basis,nw", [("B", 6), ("A", 8)])
+def test_forced_families(jkmod, torch_cuda, basis, nw):
+    """Each class forced to family 1, then family 2 (where built), with row
+    mode allowed and then off, in FP64 and mixed precision, against the
+    oracle.  The tuner may pick any of these on another device."""
+    wl = synth.small_workload(nw, basis, seed=60 + nw)
+    say("forced families", basis, nw)
+    J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
+    ej0, ek0 = o.energies(wl.D, J0, K0)
+    try:
+        for fam in (1, 2):
+            for row in (1, 2):
+                for prec in ("fp64", "mixed"):
+                    for c in jkmod.canonical_classes():
+                        for p in ("fp64", "fp32"):
+                            _, avail = jkmod.tune_get(*c, p)
+                            jkmod.tune_set(*c, p, fam if avail & fam else 0)
+                            jkmod.tune_set_row(*c, p, row)
+                    _, J, K = run_gpu(jkmod, torch_cuda, wl, precision=prec)
+                    if prec == "fp64":
+                        dj, dk = np.abs(J - J0).max(), np.abs(K - K0).max()
+                        assert dj <= TOL and dk <= TOL, (fam, row, dj, dk)
+                    else:
+                        ej, ek = o.energies(wl.D, J, K)
+                        assert abs(ej[0] - ej0[0]) <= 1e-6 and abs(ek[0] - ek0[0]) <= 1e-6, (fam, row)
+    finally:
+        for c in jkmod.canonical_classes():
+            for p in ("fp64", "fp32"):
+                jkmod.tune_set(*c, p, 0)
+                jkmod.tune_set_row(*c, p, 0)
+        jkmod.tune_load(os.path.join(os.path.dirname(jkmod.__file__), "tune_gfx950.txt"))
