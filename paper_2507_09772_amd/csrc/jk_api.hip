@@ -126,7 +126,7 @@ __global__ void k_pair_build(ShellDev sh, PairRec *pairs, int npair, PrimPair *p
                 r.P[x] = (a * A[x] + b * B[x]) / p;
                 r.PA[x] = r.P[x] - A[x];
             }
-            pp[pr.pp_off + ip * nj + jp] = r;
+            pp[pr.pp_off + (ip * nj + jp) * pr.pp_stride] = r;
         }
 }
 
@@ -316,25 +316,37 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
             for (int x = 0; x < 3; ++x) r.ab[x] = A[x] - B[x];
             by_type[stype[a] * ntype + stype[b]].push_back(r);
         }
-    std::vector<int> ptype_first, ptype_count, ptype_key;  // pair types present
-    int npp_tot = 0;
+    // Primitive pairs are stored type-major: the k-th primitive pair of the
+    // i-th pair of a type sits at base(type) + k * count(type) + i, so a wave
+    // reading consecutive pairs of one type reads consecutive records.
+    std::vector<int> ptype_first, ptype_count, ptype_key, ptype_ppbase;  // pair types present
+    int64_t npp_tot = 0;
     for (int t = 0; t < ntype * ntype; ++t) {
         if (by_type[t].empty()) continue;
         ptype_first.push_back((int)P->hpairs.size());
         ptype_count.push_back((int)by_type[t].size());
         ptype_key.push_back(t);
-        for (auto &r : by_type[t]) {
-            r.pp_off = npp_tot;
-            npp_tot += r.npp;
-            P->hpairs.push_back(r);
-        }
+        ptype_ppbase.push_back((int)npp_tot);
+        for (auto &r : by_type[t]) P->hpairs.push_back(r);
+        npp_tot += (int64_t)by_type[t].size() * by_type[t][0].npp;
     }
+    if (npp_tot > INT32_MAX) return fail(JK_EUNSUPPORTED, "too many primitive pairs");
     const int npair = (int)P->hpairs.size();
-    P->pair_of.assign((size_t)ns * ns, -1);
-    for (int p = 0; p < npair; ++p) {
-        P->pair_of[(size_t)P->hpairs[p].ish * ns + P->hpairs[p].jsh] = p;
-        P->pair_of[(size_t)P->hpairs[p].jsh * ns + P->hpairs[p].ish] = p;
-    }
+    const int npt0 = (int)ptype_first.size();
+    auto place_pairs = [&]() {
+        for (int pt = 0; pt < npt0; ++pt)
+            for (int k = 0; k < ptype_count[pt]; ++k) {
+                PairRec &r = P->hpairs[ptype_first[pt] + k];
+                r.pp_off = ptype_ppbase[pt] + k;
+                r.pp_stride = ptype_count[pt];
+            }
+        P->pair_of.assign((size_t)ns * ns, -1);
+        for (int p = 0; p < npair; ++p) {
+            P->pair_of[(size_t)P->hpairs[p].ish * ns + P->hpairs[p].jsh] = p;
+            P->pair_of[(size_t)P->hpairs[p].jsh * ns + P->hpairs[p].ish] = p;
+        }
+    };
+    place_pairs();
 
     // device copies of the basis and the pair data
     int32_t *d_l, *d_np, *d_poff, *d_atom, *d_aoc, *d_aoe;
@@ -372,6 +384,16 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
         P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)d_blk));
     }
     HIPCHK(hipMemcpy(P->hpairs.data(), P->d_pairs, sizeof(PairRec) * npair, hipMemcpyDeviceToHost));
+    // renumber the pairs of each type by q descending (ties keep their order),
+    // so each type's screening list is a contiguous id range, then rebuild
+    // the primitive pairs in that order
+    for (int pt = 0; pt < npt0; ++pt)
+        std::stable_sort(P->hpairs.begin() + ptype_first[pt], P->hpairs.begin() + ptype_first[pt] + ptype_count[pt],
+                         [](const PairRec &x, const PairRec &y) { return x.q > y.q; });
+    place_pairs();
+    HIPCHK(hipMemcpy(P->d_pairs, P->hpairs.data(), sizeof(PairRec) * npair, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_pair_build, dim3((npair + 127) / 128), dim3(128), 0, 0, P->sh, P->d_pairs, npair, P->d_pp);
+    HIPCHK(hipGetLastError());
     P->Qsh.assign((size_t)ns * ns, 0.0);
     double qmax = 0.0;
     for (auto &r : P->hpairs) {

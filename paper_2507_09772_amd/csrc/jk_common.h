@@ -34,8 +34,9 @@ JK_HD constexpr int cart_comp(int l, int idx, int axis) {
 struct PairRec {
     int32_t ish, jsh;      // shell indices
     int32_t aoi, aoj;      // Cartesian AO offsets
-    int32_t pp_off, npp;   // primitive-pair range
-    int32_t pad0, pad1;
+    int32_t pp_off, npp;   // first primitive pair, count
+    int32_t pp_stride;     // distance between its consecutive primitive pairs
+    int32_t pad1;
     double ab[3];          // A - B
     double q;              // Schwarz factor sqrt(max |(ab|ab)|)
 };

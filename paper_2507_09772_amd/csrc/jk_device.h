@@ -377,9 +377,9 @@ __device__ __forceinline__ void k1_compute(const JkArgs &a, const PairRec &B, co
     // ket primitive outer (one vector load each), bra primitive inner (the
     // bra is uniform across a tile, so its records come through scalar loads)
     for (int ik = 0; ik < npk; ++ik) {
-        const PrimPair pk = a.pp[Kt.pp_off + ik];
+        const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
         for (int ib = 0; ib < npb; ++ib) {
-            const PrimPair pb = a.pp[B.pp_off + ib];
+            const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
             const PQuart<R> g = prim_quartet<R>(pb, pk);
             R u[NR], w[NR];
             rys_roots<NR, R>(g.T, a.tab, u, w);
@@ -884,8 +884,8 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
             const bool build = pass == 0 || npq_max > 1;
             if (build) {
                 wave_sync();
-                const PrimPair pb = a.pp[B.pp_off + ib];
-                const PrimPair pk = a.pp[Kt.pp_off + ik];
+                const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
+                const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
                 const PQuart<R> g = prim_quartet<R>(pb, pk);
                 for (int t = sl; t < 3 * NR && lane_used; t += LPQ) {
                     const int r = t / 3, x = t % 3;
