@@ -38,6 +38,11 @@
  * linear combinations of Cartesian ones), built here from the closed formula
  * for real solid harmonics and normalised numerically.
  *
+ * Range separation (the paper's omega, Tables 1 and 2): the same contraction
+ * over the long-range operator erf(omega r)/r (omega > 0) or the short-range
+ * operator erfc(|omega| r)/r (omega < 0), through the attenuated Boys values
+ * of op_boys; screening keeps the full-range Schwarz factors.
+ *
  * Parity pins live in tests/test_oracle_*.py.
  */
 #include <math.h>
@@ -65,6 +70,7 @@ typedef struct {
     int *coff;      /* Cartesian AO offset */
     int *eoff;      /* external (spherical or Cartesian) AO offset */
     int nao_cart, nao_ext;
+    double omega;   /* operator: 0 full range, > 0 long range, < 0 short range */
 } obasis;
 
 static int ob_init(obasis *b, int ns, int natom, int spherical, const int *l, const int *nprim,
@@ -72,6 +78,7 @@ static int ob_init(obasis *b, int ns, int natom, int spherical, const int *l, co
     b->ns = ns; b->natom = natom; b->spherical = spherical;
     b->l = l; b->nprim = nprim; b->atom = atom;
     b->exps = exps; b->coefs = coefs; b->coords = coords;
+    b->omega = 0.0;
     b->poff = (int *)malloc(sizeof(int) * (ns + 1));
     b->coff = (int *)malloc(sizeof(int) * (ns + 1));
     b->eoff = (int *)malloc(sizeof(int) * (ns + 1));
@@ -126,6 +133,32 @@ void oracle_boys(int mmax, double T, double *F) {
 }
 
 /* ------------------------------------------------------------------ */
+/* Range-separated operators (the paper's range-separation parameter    */
+/* omega, Table 1 rys_type and Table 2).  With the Gaussian transform   */
+/* 1/r = (2/sqrt(pi)) int_0^inf exp(-s^2 r^2) ds, the error-function    */
+/* operator erf(w r)/r keeps s in [0, w]; in the Boys variable t^2 =    */
+/* s^2 / (alpha + s^2) that is t in [0, theta], theta^2 = w^2/(w^2 +    */
+/* alpha), and int_0^theta t^(2n) exp(-T t^2) dt = theta^(2n+1)          */
+/* F_n(theta^2 T).  These satisfy the same derivative relation as F_n,  */
+/* so R^n_000 = (-2 alpha)^n Ftilde_n(T) carries over unchanged.        */
+/*   omega > 0: long range  erf(omega r)/r:  Ftilde_n = theta^(2n+1) F_n(theta^2 T)       */
+/*   omega < 0: short range erfc(|omega| r)/r: Ftilde_n = F_n(T) - (the long-range one)  */
+/* ------------------------------------------------------------------ */
+static void op_boys(int mmax, double T, double alpha, double omega, double *F) {
+    oracle_boys(mmax, T, F);
+    if (omega == 0.0) return;
+    const double w2 = omega * omega, th2 = w2 / (w2 + alpha);
+    double G[4 * OR_LMAX + 1];
+    oracle_boys(mmax, th2 * T, G);
+    double f = sqrt(th2);
+    for (int n = 0; n <= mmax; ++n) {
+        const double lr = f * G[n];
+        F[n] = omega > 0.0 ? lr : F[n] - lr;
+        f *= th2;
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* McMurchie-Davidson pieces                                            */
 /* ------------------------------------------------------------------ */
 #define E_DIM (OR_LMAX + 1)
@@ -165,9 +198,9 @@ static void md_E(int la, int lb, double p, double PA, double PB, double E[E_DIM]
 
 /* Hermite Coulomb integrals R_tuv = R^0_tuv for t+u+v <= L.
  * work: R_DIM^4 doubles. out: R_DIM^3 doubles indexed (t*R_DIM+u)*R_DIM+v. */
-static void md_R(int L, double alpha, double X, double Y, double Z, double *work, double *out) {
+static void md_R(int L, double alpha, double omega, double X, double Y, double Z, double *work, double *out) {
     double F[OR_LTOT + 1];
-    oracle_boys(L, alpha * (X * X + Y * Y + Z * Z), F);
+    op_boys(L, alpha * (X * X + Y * Y + Z * Z), alpha, omega, F);
     double f = 1.0;
     for (int n = 0; n <= L; ++n) { work[RIDX(n, 0, 0, 0)] = f * F[n]; f *= -2.0 * alpha; }
     for (int s = 1; s <= L; ++s)
@@ -244,7 +277,7 @@ static void eri_block(const obasis *B, int I, int J, int K, int L, double *out, 
                         md_E(lk, ll, q, Q[x] - C[x], Q[x] - Dc[x], Ecd[x]);
                     }
                     const double alpha = p * q / (p + q);
-                    md_R(Ltot, alpha, P[0] - Q[0], P[1] - Q[1], P[2] - Q[2], ws->rwork, ws->R);
+                    md_R(Ltot, alpha, B->omega, P[0] - Q[0], P[1] - Q[1], P[2] - Q[2], ws->rwork, ws->R);
                     const double pref = 2.0 * pow(OR_PI, 2.5) / (p * q * sqrt(p + q)) * kab * kcd;
                     /* ket first: W[tuv][cd] */
                     for (int cd = 0; cd < ncd; ++cd) {
@@ -354,13 +387,19 @@ int oracle_nao(BASIS_ARGS, int *nao_ext, int *nao_cart) {
     return 0;
 }
 
-/* Cartesian contracted block (IJ|KL) into out[ni*nj*nk*nl]. */
-int oracle_eri_block(BASIS_ARGS, int I, int J, int K, int L, double *out) {
+/* Cartesian contracted block (IJ|KL) into out[ni*nj*nk*nl]; omega selects
+ * the operator (0 full range, > 0 erf(omega r)/r, < 0 erfc(|omega| r)/r). */
+int oracle_eri_block_op(BASIS_ARGS, double omega, int I, int J, int K, int L, double *out) {
     obasis b; md_ws w;
     if (ob_init(&b, BASIS_PASS) || ws_init(&w)) return -1;
+    b.omega = omega;
     eri_block(&b, I, J, K, L, out, &w);
     ws_free(&w); ob_free(&b);
     return 0;
+}
+
+int oracle_eri_block(BASIS_ARGS, int I, int J, int K, int L, double *out) {
+    return oracle_eri_block_op(BASIS_PASS, 0.0, I, J, K, L, out);
 }
 
 /* Schwarz table Q[I*ns+J] = sqrt(max_{a in I, b in J} |(ab|ab)|). */
@@ -449,8 +488,8 @@ static void load_c2s(double store[OR_LMAX + 1][OR_MAXNC * (2 * OR_LMAX + 1)], co
  * 1 eight-fold.  *nsig receives the number of significant unique shell
  * quartets (I>=J, K>=L, IJ>=KL) in either mode.
  */
-int oracle_jk(BASIS_ARGS, const double *D, int nset, double cutoff, const double *Qin, int mode,
-              double *Jout, double *Kout, long long *nsig) {
+int oracle_jk_op(BASIS_ARGS, double omega, const double *D, int nset, double cutoff, const double *Qin, int mode,
+                 double *Jout, double *Kout, long long *nsig) {
     obasis b;
     if (ob_init(&b, BASIS_PASS)) return -1;
     const int ns_ = b.ns, nc = b.nao_cart, ne = b.nao_ext;
@@ -458,7 +497,11 @@ int oracle_jk(BASIS_ARGS, const double *D, int nset, double cutoff, const double
     const double *Tl[OR_LMAX + 1];
     load_c2s(c2s_store, Tl);
     double *Q = (double *)malloc(sizeof(double) * ns_ * ns_);
+    /* screening always by the full-range Schwarz factors: they bound the
+     * long- and short-range integrals too (both operators are 1/r minus a
+     * positive semidefinite kernel) */
     if (Qin) memcpy(Q, Qin, sizeof(double) * ns_ * ns_); else schwarz(&b, Q);
+    b.omega = omega;
     double *Dc = (double *)malloc(sizeof(double) * nset * nc * nc);
     double *Jc = (double *)calloc((size_t)nset * nc * nc, sizeof(double));
     double *Kc = (double *)calloc((size_t)nset * nc * nc, sizeof(double));
@@ -561,6 +604,11 @@ int oracle_jk(BASIS_ARGS, const double *D, int nset, double cutoff, const double
     if (nsig) *nsig = count;
     free(Q); free(Dc); free(Jc); free(Kc); ob_free(&b);
     return 0;
+}
+
+int oracle_jk(BASIS_ARGS, const double *D, int nset, double cutoff, const double *Qin, int mode,
+              double *Jout, double *Kout, long long *nsig) {
+    return oracle_jk_op(BASIS_PASS, 0.0, D, nset, cutoff, Qin, mode, Jout, Kout, nsig);
 }
 
 /*

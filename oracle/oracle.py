@@ -101,13 +101,15 @@ def nao(mol) -> tuple[int, int]:
     return ne.value, nc.value
 
 
-def eri_block(mol, I: int, J: int, K: int, L: int) -> np.ndarray:
-    """Contracted Cartesian block (IJ|KL), shape [nI, nJ, nK, nL]."""
+def eri_block(mol, I: int, J: int, K: int, L: int, omega: float = 0.0) -> np.ndarray:
+    """Contracted Cartesian block (IJ|KL), shape [nI, nJ, nK, nL], over the
+    operator 1/r (omega = 0), erf(omega r)/r (omega > 0) or
+    erfc(|omega| r)/r (omega < 0)."""
     b = _Basis(mol)
     nc = [(int(mol.l[x]) + 1) * (int(mol.l[x]) + 2) // 2 for x in (I, J, K, L)]
     out = np.zeros(nc)
-    rc = _load().oracle_eri_block(*b.args(), ctypes.c_int(I), ctypes.c_int(J), ctypes.c_int(K),
-                                  ctypes.c_int(L), _dp(out))
+    rc = _load().oracle_eri_block_op(*b.args(), ctypes.c_double(omega), ctypes.c_int(I), ctypes.c_int(J),
+                                     ctypes.c_int(K), ctypes.c_int(L), _dp(out))
     if rc:
         raise ValueError("invalid basis")
     return out
@@ -122,9 +124,12 @@ def schwarz(mol) -> np.ndarray:
     return Q
 
 
-def jk(mol, D: np.ndarray, cutoff: float = 1e-13, mode: int = 1, Q: np.ndarray | None = None):
+def jk(mol, D: np.ndarray, cutoff: float = 1e-13, mode: int = 1, Q: np.ndarray | None = None,
+       omega: float = 0.0):
     """Full J, K ([nset, nao, nao] each) and the number of significant unique
-    shell quartets.  mode 0: every ordered quartet; mode 1: eight-fold."""
+    shell quartets.  mode 0: every ordered quartet; mode 1: eight-fold.
+    omega selects the operator as in eri_block; the Schwarz screening always
+    uses the full-range factors."""
     b = _Basis(mol)
     D = np.ascontiguousarray(D, dtype=np.float64)
     if D.ndim == 2:
@@ -137,8 +142,8 @@ def jk(mol, D: np.ndarray, cutoff: float = 1e-13, mode: int = 1, Q: np.ndarray |
     if Q is not None:
         Qc = np.ascontiguousarray(Q, dtype=np.float64)
         qp = _dp(Qc)
-    rc = _load().oracle_jk(*b.args(), _dp(D), ctypes.c_int(nset), ctypes.c_double(cutoff), qp,
-                           ctypes.c_int(mode), _dp(J), _dp(K), ctypes.byref(cnt))
+    rc = _load().oracle_jk_op(*b.args(), ctypes.c_double(omega), _dp(D), ctypes.c_int(nset),
+                              ctypes.c_double(cutoff), qp, ctypes.c_int(mode), _dp(J), _dp(K), ctypes.byref(cnt))
     if rc:
         raise ValueError("invalid basis")
     return J, K, int(cnt.value)
