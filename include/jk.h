@@ -41,7 +41,7 @@ extern "C" {
 enum {
     JK_OK = 0,
     JK_EINVAL = -1,        /* bad argument: sizes, ranges, non-finite values */
-    JK_EUNSUPPORTED = -2,  /* valid but not implemented (omega != 0, l > JK_LMAX) */
+    JK_EUNSUPPORTED = -2,  /* valid but not implemented (l > JK_LMAX) */
     JK_ENOMEM = -3,        /* device or host allocation failed */
     JK_EDEVICE = -4        /* a HIP call failed */
 };
@@ -117,7 +117,11 @@ int jk_plan_schwarz(const jk_plan *plan, double *Q_host);
  * J and K are overwritten unless JK_ACCUMULATE; either may be NULL when the
  * matching JK_DO_* flag is clear.  precision: JK_FP64 / JK_MIXED / JK_FP32;
  * mix_threshold: bound below which JK_MIXED uses FP32 (ignored otherwise).
- * omega must be 0 (range separation -> JK_EUNSUPPORTED).  Asynchronous on
+ * omega selects the operator (the range-separation parameter of Table 2,
+ * rys_type of Table 1): 0 the Coulomb operator 1/r, > 0 the long-range
+ * erf(omega r)/r, < 0 the short-range erfc(|omega| r)/r; the screening uses
+ * the Coulomb Schwarz factors in every case (they bound both parts); non-
+ * finite omega -> JK_EINVAL.  Asynchronous on
  * stream; D/J/K must stay valid until the stream reaches this point.
  * nset >= 1.
  */

@@ -749,7 +749,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     if ((do_j && !J) || (do_k && !K)) return fail(JK_EINVAL, "J/K output missing for a requested matrix");
     if (precision != JK_FP64 && precision != JK_MIXED && precision != JK_FP32) return fail(JK_EINVAL, "bad precision %d", precision);
     if (precision == JK_MIXED && !(std::isfinite(mix_threshold) && mix_threshold >= 0.0)) return fail(JK_EINVAL, "mix_threshold must be finite and >= 0");
-    if (omega != 0.0) return fail(JK_EUNSUPPORTED, "range-separated Coulomb (omega != 0) is not implemented");
+    if (!std::isfinite(omega)) return fail(JK_EINVAL, "omega must be finite");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     if (dev != P->device) return fail(JK_EINVAL, "plan was created on device %d, current device is %d", P->device, dev);
@@ -784,6 +784,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     a.dmax = P->d_dmax;
     a.nshell = P->ns;
     a.mix_thr = mix_threshold;
+    a.omega = omega;
     a.tab = P->tab;
     if (precision == JK_MIXED) {
         if (!P->d_list) {

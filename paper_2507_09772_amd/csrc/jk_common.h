@@ -126,6 +126,8 @@ struct JkArgs {
     const float *dmax;   // [nshell][nshell] max |D| over the block and densities
     int32_t nshell, sel;
     double mix_thr;
+    // operator: 0 Coulomb, > 0 erf(omega r)/r, < 0 erfc(|omega| r)/r
+    double omega;
     Tables tab;
 };
 

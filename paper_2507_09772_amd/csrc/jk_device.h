@@ -175,6 +175,52 @@ __device__ __forceinline__ void rys_root1(double T, int r, const Tables &tab, R 
 }
 
 // ---------------------------------------------------------------------------
+// Range separation (the range-separation parameter omega).  The integrand of
+// the long-range operator erf(omega r)/r is the Coulomb one restricted to
+// t in [0, theta], theta^2 = omega^2 / (omega^2 + rho): substituting t =
+// theta s turns it into a standard Rys rule at theta^2 T whose roots t^2 are
+// theta^2 times the standard roots and whose weights carry a factor theta.
+// The short-range operator erfc(|omega| r)/r is the full one minus the long
+// one.  A primitive quartet is therefore evaluated as one or two "variants":
+//   omega = 0: variant 0 (full range);  omega > 0: variant 1 (long range);
+//   omega < 0: variant 0 plus variant 1 with negated weights.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int variant_begin(double omega) { return omega > 0.0 ? 1 : 0; }
+__device__ __forceinline__ int variant_end(double omega) { return omega == 0.0 ? 1 : 2; }
+
+template <int N, typename R>
+__device__ __forceinline__ void rys_roots_op(double T, double rho, double omega, int variant, const Tables &tab,
+                                             R (&u)[N], R (&w)[N]) {
+    if (variant == 0) {
+        rys_roots<N, R>(T, tab, u, w);
+        return;
+    }
+    const double w2 = omega * omega, th2 = w2 / (w2 + rho);
+    rys_roots<N, R>(th2 * T, tab, u, w);
+    const double th = sqrt(th2);
+    const R su = (R)th2, sw = (R)(omega > 0.0 ? th : -th);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        u[i] *= su;
+        w[i] *= sw;
+    }
+}
+
+template <int N, typename R>
+__device__ __forceinline__ void rys_root1_op(double T, double rho, double omega, int variant, int r,
+                                             const Tables &tab, R &u, R &w) {
+    if (variant == 0) {
+        rys_root1<N, R>(T, r, tab, u, w);
+        return;
+    }
+    const double w2 = omega * omega, th2 = w2 / (w2 + rho);
+    rys_root1<N, R>(th2 * T, r, tab, u, w);
+    const double th = sqrt(th2);
+    u *= (R)th2;
+    w *= (R)(omega > 0.0 ? th : -th);
+}
+
+// ---------------------------------------------------------------------------
 // 2-D integrals of one direction for one root: vertical recurrence G(n, m)
 // scaled by s, then horizontal transfers; emit(a, b, c, d, value) receives
 // every I(a, b, c, d), a <= LI, b <= LJ, c <= LK, d <= LL, in b-major order.
@@ -326,7 +372,7 @@ __device__ __forceinline__ double pair_weight(int bra, int ket, const PairRec &B
 // FP64 and rounded to R afterwards.
 template <typename R>
 struct PQuart {
-    double T;
+    double T, rho;  // T = rho |PQ|^2, rho = pq / (p + q)
     R fq, fp, rpq, pref, hb, hk;
     R PQ[3], PA[3], QC[3];
 };
@@ -343,7 +389,8 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
         d[x] = pb.P[x] - pk.P[x];
         pq2 += d[x] * d[x];
     }
-    g.T = p * q * rpq * pq2;
+    g.rho = p * q * rpq;
+    g.T = g.rho * pq2;
     g.rpq = (R)rpq;
     g.fq = (R)(q * rpq);
     g.fp = (R)(p * rpq);
@@ -381,8 +428,9 @@ __device__ __forceinline__ void k1_compute(const JkArgs &a, const PairRec &B, co
         for (int ib = 0; ib < npb; ++ib) {
             const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
             const PQuart<R> g = prim_quartet<R>(pb, pk);
+            for (int var = variant_begin(a.omega); var < variant_end(a.omega); ++var) {
             R u[NR], w[NR];
-            rys_roots<NR, R>(g.T, a.tab, u, w);
+            rys_roots_op<NR, R>(g.T, g.rho, a.omega, var, a.tab, u, w);
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 const R t = u[r];
@@ -412,6 +460,7 @@ __device__ __forceinline__ void k1_compute(const JkArgs &a, const PairRec &B, co
                                 const int iz = C::t4(cart_comp(LI, i, 2), cart_comp(LJ, j, 2), cart_comp(LK, k, 2), cart_comp(LL, l, 2));
                                 V[((i * NJ + j) * NK + k) * NL + l] += I[0][ix] * I[1][iy] * I[2][iz];
                             }
+            }
             }
         }
     }
@@ -876,12 +925,15 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
 #pragma unroll
                 for (int d = 0; d < NL; ++d) acc[k][bb][d] = (R)0;
 
-        for (int ipq = 0; ipq < npq_max; ++ipq) {
+        // every primitive quartet once per operator variant
+        const int vb = variant_begin(a.omega), nv = variant_end(a.omega) - vb;
+        for (int it = 0; it < npq_max * nv; ++it) {
+            const int ipq = it / nv, var = vb + it % nv;
             const bool has = ipq < npq;
             const int ib = has ? ipq % npb : 0, ik = has ? ipq / npb : 0;
-            // with a single primitive quartet per quartet the tables of
-            // pass 0 are reused by the later passes
-            const bool build = pass == 0 || npq_max > 1;
+            // with a single table set per quartet the tables of pass 0 are
+            // reused by the later passes
+            const bool build = pass == 0 || npq_max * nv > 1;
             if (build) {
                 wave_sync();
                 const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
@@ -890,7 +942,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                 for (int t = sl; t < 3 * NR && lane_used; t += LPQ) {
                     const int r = t / 3, x = t % 3;
                     R u, w;
-                    rys_root1<NR, R>(g.T, r, a.tab, u, w);
+                    rys_root1_op<NR, R>(g.T, g.rho, a.omega, var, r, a.tab, u, w);
                     const R b00 = (R)0.5 * u * g.rpq;
                     const R b10 = g.hb * ((R)1 - g.fq * u);
                     const R b01 = g.hk * ((R)1 - g.fp * u);

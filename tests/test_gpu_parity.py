@@ -165,8 +165,25 @@ def test_flags_and_accumulate(jkmod, torch_cuda):
     assert torch.allclose(Jo, J, atol=1e-14) and torch.allclose(Ko, K, atol=1e-14)
     assert torch.allclose(J2, 2 * J, atol=1e-13) and torch.allclose(K2, 2 * K, atol=1e-13)
     with pytest.raises(jkmod.JKError) as e:
-        plan.execute(D, omega=0.3)
-    assert e.value.code == jkmod.JK_EUNSUPPORTED
+        plan.execute(D, omega=float("nan"))
+    assert e.value.code == jkmod.JK_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# range separation: long range erf(w r)/r (w > 0), short range erfc (w < 0)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("basis,nw,omega", [("A", 4, 0.4), ("A", 4, -0.4), ("B", 3, 0.25), ("B", 3, -0.25),
+                                            ("B", 6, -0.4), ("A", 8, 0.3)])
+def test_range_separated(jkmod, torch_cuda, basis, nw, omega):
+    wl = synth.small_workload(nw, basis, seed=90 + nw, nset=2)
+    say("range separated", basis, nw, omega)
+    J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, omega=omega)
+    plan, J, K = run_gpu(jkmod, torch_cuda, wl, omega=omega)
+    assert np.abs(J - J0).max() <= TOL and np.abs(K - K0).max() <= TOL
+    ej0, ek0 = o.energies(wl.D, J0, K0)
+    _, Jm, Km = run_gpu(jkmod, torch_cuda, wl, precision="mixed", plan=plan, omega=omega)
+    ej, ek = o.energies(wl.D, Jm, Km)
+    assert np.abs(ej - ej0).max() <= 1e-6 and np.abs(ek - ek0).max() <= 1e-6
 
 
 # ---------------------------------------------------------------------------
@@ -234,9 +251,16 @@ def test_forced_families(jkmod, torch_cuda, basis, nw):
     say("forced families", basis, nw)
     J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
     ej0, ek0 = o.energies(wl.D, J0, K0)
+    Js0, Ks0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, omega=-0.4)
     try:
         for fam in (1, 2):
             for row in (1, 2):
+                for c in jkmod.canonical_classes():
+                    _, avail = jkmod.tune_get(*c, "fp64")
+                    jkmod.tune_set(*c, "fp64", fam if avail & fam else 0)
+                    jkmod.tune_set_row(*c, "fp64", row)
+                _, Js, Ks = run_gpu(jkmod, torch_cuda, wl, omega=-0.4)
+                assert np.abs(Js - Js0).max() <= TOL and np.abs(Ks - Ks0).max() <= TOL, ("short range", fam, row)
                 for prec in ("fp64", "mixed"):
                     for c in jkmod.canonical_classes():
                         for p in ("fp64", "fp32"):
