@@ -488,8 +488,51 @@ static void load_c2s(double store[OR_LMAX + 1][OR_MAXNC * (2 * OR_LMAX + 1)], co
  * 1 eight-fold.  *nsig receives the number of significant unique shell
  * quartets (I>=J, K>=L, IJ>=KL) in either mode.
  */
+/*
+ * Density screening (the direct-SCF screening by the density matrix, at
+ * shell-pair level like the Schwarz test): with dscreen > 0 a quartet is
+ * kept only if Q_IJ Q_KL max(Dm_IJ, Dm_KL, Dm_IK, Dm_IL, Dm_JK, Dm_JL) >=
+ * dscreen, Dm_XY = max over densities and the Cartesian components of the
+ * block (X, Y) of |D| (the Cartesian density, single precision, the
+ * precision the GPU library takes this decision in).  Applied to a density
+ * change Delta D this is the incremental-SCF screening; it bounds every
+ * dropped contribution to J and K by dscreen.
+ */
+static double *dmax_table(const obasis *b, const double *Dc, int nset) {
+    const int ns = b->ns, nc = b->nao_cart;
+    double *dm = (double *)malloc(sizeof(double) * ns * ns);
+    for (int I = 0; I < ns; ++I)
+        for (int J = 0; J < ns; ++J) {
+            double m = 0.0;
+            for (int s = 0; s < nset; ++s)
+                for (int a = b->coff[I]; a < b->coff[I + 1]; ++a)
+                    for (int c = b->coff[J]; c < b->coff[J + 1]; ++c) m = fmax(m, fabs(Dc[(size_t)s * nc * nc + (size_t)a * nc + c]));
+            dm[I * ns + J] = (double)(float)m;
+        }
+    return dm;
+}
+
+static int density_kept(const double *Q, const double *dm, int ns, double dscreen, int I, int J, int K, int L) {
+    if (dscreen <= 0.0) return 1;
+    double m = dm[I * ns + J];
+    m = fmax(m, dm[K * ns + L]);
+    m = fmax(m, dm[I * ns + K]);
+    m = fmax(m, dm[I * ns + L]);
+    m = fmax(m, dm[J * ns + K]);
+    m = fmax(m, dm[J * ns + L]);
+    return Q[I * ns + J] * Q[K * ns + L] * m >= dscreen;
+}
+
+int oracle_jk_screen(BASIS_ARGS, double omega, double dscreen, const double *D, int nset, double cutoff,
+                     const double *Qin, int mode, double *Jout, double *Kout, long long *nsig);
+
 int oracle_jk_op(BASIS_ARGS, double omega, const double *D, int nset, double cutoff, const double *Qin, int mode,
                  double *Jout, double *Kout, long long *nsig) {
+    return oracle_jk_screen(BASIS_PASS, omega, 0.0, D, nset, cutoff, Qin, mode, Jout, Kout, nsig);
+}
+
+int oracle_jk_screen(BASIS_ARGS, double omega, double dscreen, const double *D, int nset, double cutoff,
+                     const double *Qin, int mode, double *Jout, double *Kout, long long *nsig) {
     obasis b;
     if (ob_init(&b, BASIS_PASS)) return -1;
     const int ns_ = b.ns, nc = b.nao_cart, ne = b.nao_ext;
@@ -506,6 +549,7 @@ int oracle_jk_op(BASIS_ARGS, double omega, const double *D, int nset, double cut
     double *Jc = (double *)calloc((size_t)nset * nc * nc, sizeof(double));
     double *Kc = (double *)calloc((size_t)nset * nc * nc, sizeof(double));
     for (int s = 0; s < nset; ++s) d_to_cart(&b, D + (size_t)s * ne * ne, Dc + (size_t)s * nc * nc, Tl);
+    double *dm = dmax_table(&b, Dc, nset);
     long long count = 0;
     const int npair = ns_ * (ns_ + 1) / 2;
 #pragma omp parallel reduction(+ : count)
@@ -521,6 +565,7 @@ int oracle_jk_op(BASIS_ARGS, double omega, const double *D, int nset, double cut
                 for (int K = 0; K < ns_; ++K)
                     for (int L = 0; L < ns_; ++L) {
                         if (Q[I * ns_ + J] * Q[K * ns_ + L] < cutoff) continue;
+                        if (!density_kept(Q, dm, ns_, dscreen, I, J, K, L)) continue;
                         if (I >= J && K >= L && I * (I + 1) / 2 + J >= K * (K + 1) / 2 + L) ++count;
                         eri_block(&b, I, J, K, L, blk, &w);
                         const int ni = OR_NC(b.l[I]), nj = OR_NC(b.l[J]), nk = OR_NC(b.l[K]), nl = OR_NC(b.l[L]);
@@ -552,6 +597,7 @@ int oracle_jk_op(BASIS_ARGS, double omega, const double *D, int nset, double cut
                     while ((K + 1) * (K + 2) / 2 <= kl) ++K;
                     const int L = kl - K * (K + 1) / 2;
                     if (Q[I * ns_ + J] * Q[K * ns_ + L] < cutoff) continue;
+                    if (!density_kept(Q, dm, ns_, dscreen, I, J, K, L)) continue;
                     ++count;
                     double wgt = 1.0;
                     if (I == J) wgt *= 0.5;
@@ -602,7 +648,7 @@ int oracle_jk_op(BASIS_ARGS, double omega, const double *D, int nset, double cut
         mat_to_ext(&b, Kc + (size_t)s * nc * nc, Kout + (size_t)s * ne * ne, Tl);
     }
     if (nsig) *nsig = count;
-    free(Q); free(Dc); free(Jc); free(Kc); ob_free(&b);
+    free(dm); free(Q); free(Dc); free(Jc); free(Kc); ob_free(&b);
     return 0;
 }
 

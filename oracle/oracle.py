@@ -125,11 +125,12 @@ def schwarz(mol) -> np.ndarray:
 
 
 def jk(mol, D: np.ndarray, cutoff: float = 1e-13, mode: int = 1, Q: np.ndarray | None = None,
-       omega: float = 0.0):
+       omega: float = 0.0, dscreen: float = 0.0):
     """Full J, K ([nset, nao, nao] each) and the number of significant unique
     shell quartets.  mode 0: every ordered quartet; mode 1: eight-fold.
     omega selects the operator as in eri_block; the Schwarz screening always
-    uses the full-range factors."""
+    uses the full-range factors.  dscreen > 0 adds the density screening
+    Q_IJ Q_KL max|D over the six blocks| >= dscreen."""
     b = _Basis(mol)
     D = np.ascontiguousarray(D, dtype=np.float64)
     if D.ndim == 2:
@@ -142,8 +143,9 @@ def jk(mol, D: np.ndarray, cutoff: float = 1e-13, mode: int = 1, Q: np.ndarray |
     if Q is not None:
         Qc = np.ascontiguousarray(Q, dtype=np.float64)
         qp = _dp(Qc)
-    rc = _load().oracle_jk_op(*b.args(), ctypes.c_double(omega), _dp(D), ctypes.c_int(nset),
-                              ctypes.c_double(cutoff), qp, ctypes.c_int(mode), _dp(J), _dp(K), ctypes.byref(cnt))
+    rc = _load().oracle_jk_screen(*b.args(), ctypes.c_double(omega), ctypes.c_double(dscreen), _dp(D),
+                                  ctypes.c_int(nset), ctypes.c_double(cutoff), qp, ctypes.c_int(mode), _dp(J), _dp(K),
+                                  ctypes.byref(cnt))
     if rc:
         raise ValueError("invalid basis")
     return J, K, int(cnt.value)
