@@ -128,6 +128,20 @@ int jk_plan_schwarz(const jk_plan *plan, double *Q_host);
 int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int32_t precision,
                double mix_threshold, double omega, double *J, double *K, void *stream);
 
+/*
+ * Density screening for direct SCF (Section 2: the screening of the J and K
+ * changes by the density change, at shell-pair level).  With threshold > 0,
+ * later jk_execute calls on this plan drop every quartet with
+ *   Q_IJ Q_KL max(Dm_IJ, Dm_KL, Dm_IK, Dm_IL, Dm_JK, Dm_JL) < threshold,
+ * Dm_XY the largest |D| over the densities and the Cartesian components of
+ * block (X, Y) (single precision), so each dropped contribution to any J or
+ * K element is below the threshold.  Passing the density change Delta D with
+ * JK_ACCUMULATE builds the incremental J += Delta J, K += Delta K.
+ * threshold = 0 turns it off (the default).  JK_EINVAL for a NULL plan or a
+ * negative / non-finite threshold.
+ */
+int jk_plan_set_density_screening(jk_plan *plan, double threshold);
+
 /* One-shot: plan_create + execute (J and K) + synchronise + destroy. */
 int jk_build(const jk_basis *basis, const double *D, int32_t nset, double cutoff, int32_t precision,
              double *J, double *K, void *stream);

@@ -766,7 +766,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Jc, (int64_t)(nset * m), 0.0);
     hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Kc, (int64_t)(nset * m), 0.0);
     HIPCHK(hipGetLastError());
-    if (precision == JK_MIXED) {
+    if (precision == JK_MIXED || P->dscreen > 0.0) {
         hipLaunchKernelGGL(k_dmax, dim3((P->ns * P->ns + 255) / 256), dim3(256), 0, s, Dc, P->maps.aoc, P->maps.l, P->ns, P->naoc, nset, P->d_dmax);
         HIPCHK(hipGetLastError());
     }
@@ -785,6 +785,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     a.nshell = P->ns;
     a.mix_thr = mix_threshold;
     a.omega = omega;
+    a.dscreen = P->dscreen;
     a.tab = P->tab;
     if (precision == JK_MIXED) {
         if (!P->d_list) {
@@ -885,6 +886,13 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     if (do_j) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Jc, J, P->nao, P->naoc, nset, P->sph, acc);
     if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Kc, K, P->nao, P->naoc, nset, P->sph, acc);
     HIPCHK(hipGetLastError());
+    return JK_OK;
+}
+
+extern "C" int jk_plan_set_density_screening(jk_plan *P, double threshold) {
+    if (!P) return fail(JK_EINVAL, "plan is NULL");
+    if (!(std::isfinite(threshold) && threshold >= 0.0)) return fail(JK_EINVAL, "threshold must be finite and >= 0");
+    P->dscreen = threshold;
     return JK_OK;
 }
 

@@ -128,6 +128,8 @@ struct JkArgs {
     double mix_thr;
     // operator: 0 Coulomb, > 0 erf(omega r)/r, < 0 erfc(|omega| r)/r
     double omega;
+    // density screening threshold on Q_IJ Q_KL max|D_block| (0: off)
+    double dscreen;
     Tables tab;
 };
 

@@ -356,8 +356,23 @@ __device__ __forceinline__ void list_append(const JkArgs &a, bool push, int bra,
     }
 }
 
-__device__ __forceinline__ bool above_threshold(const JkArgs &a, const PairRec &B, const PairRec &K) {
-    return B.q * K.q * (double)dmax6(a, B, K) >= a.mix_thr;
+// Screening and precision split of one quartet from its bound
+// Q_IJ Q_KL max|D| over the six blocks it touches: below dscreen (> 0) the
+// quartet is dropped (density screening); in the FP32 pass of the mixed
+// split a quartet at or above mix_thr is marked hi (it goes to the FP64
+// list instead).  Both decisions are uniform in the class, so the branch on
+// them is too.
+__device__ __forceinline__ void screen_quartet(const JkArgs &a, const PairRec &B, const PairRec &K, bool &valid,
+                                               bool &hi) {
+    hi = false;
+    if (a.dscreen > 0.0 || a.sel == SEL_LOW) {
+        const double bound = B.q * K.q * (double)dmax6(a, B, K);
+        if (a.dscreen > 0.0) valid = valid && bound >= a.dscreen;
+        if (a.sel == SEL_LOW) {
+            hi = valid && bound >= a.mix_thr;
+            valid = valid && !hi;
+        }
+    }
 }
 
 __device__ __forceinline__ double pair_weight(int bra, int ket, const PairRec &B, const PairRec &K) {
@@ -618,11 +633,9 @@ __device__ __forceinline__ void k1_tile(const JkArgs &a, int wave) {
         const PairRec &B = a.pairs[bra];
         const PairRec &Kt = a.pairs[ket];
         const double wq = pair_weight(bra, ket, B, Kt);
-        if (a.sel == SEL_LOW) {
-            const bool hi = valid && above_threshold(a, B, Kt);
-            list_append(a, hi, bra, ket);
-            valid = valid && !hi;
-        }
+        bool hi;
+        screen_quartet(a, B, Kt, valid, hi);
+        if (a.sel == SEL_LOW) list_append(a, hi, bra, ket);
         k1_body<LI, LJ, LK, LL, R, MODE_JK>(a, bra, ket, valid, wq, 0);
     }
 }
@@ -682,11 +695,9 @@ __global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
         const int ket = a.ket_list[valid ? j : cnt - 1];
         const PairRec Kt = a.pairs[ket];
         const double wq = pair_weight(bra, ket, B, Kt);
-        if (a.sel == SEL_LOW) {
-            const bool hi = valid && above_threshold(a, B, Kt);
-            list_append(a, hi, bra, ket);
-            valid = valid && !hi;
-        }
+        bool hi;
+        screen_quartet(a, B, Kt, valid, hi);
+        if (a.sel == SEL_LOW) list_append(a, hi, bra, ket);
         R V[C::NC];
         k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, a.npb, a.npk, V);
         const int cK = a.tpos[Kt.ish] * NK, cL = segL + a.tpos[Kt.jsh] * NL;
@@ -1087,11 +1098,9 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
         const PairRec &B_ = (a).pairs[bra_];                                    \
         const PairRec &K_ = (a).pairs[ket_];                                    \
         const double wq_ = pair_weight(bra_, ket_, B_, K_);                     \
-        if ((a).sel == SEL_LOW) {                                               \
-            const bool hi_ = valid_ && above_threshold((a), B_, K_);            \
-            list_append((a), hi_ && sl == 0, bra_, ket_);                       \
-            valid_ = valid_ && !hi_;                                            \
-        }                                                                       \
+        bool hi_;                                                               \
+        screen_quartet((a), B_, K_, valid_, hi_);                               \
+        if ((a).sel == SEL_LOW) list_append((a), hi_ && sl == 0, bra_, ket_);   \
         k2_body<LI, LJ, LK, LL, R, MODE_JK>((a), tabs, dig, bra_, ket_, valid_, wq_, 0); \
     } while (0)
 
@@ -1171,11 +1180,9 @@ __global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
         const int ket = a.ket_list[j < cnt ? j : cnt - 1];
         const PairRec &Kt = a.pairs[ket];
         const double wq = pair_weight(bra, ket, B, Kt);
-        if (a.sel == SEL_LOW) {
-            const bool hi = valid && above_threshold(a, B, Kt);
-            list_append(a, hi && sl == 0, bra, ket);
-            valid = valid && !hi;
-        }
+        bool hi;
+        screen_quartet(a, B, Kt, valid, hi);
+        if (a.sel == SEL_LOW) list_append(a, hi && sl == 0, bra, ket);
         k2_body<LI, LJ, LK, LL, R, MODE_JK, true>(a, tabs, dig, bra, ket, valid, wq, 0, rows, ncols, segL);
     }
     __syncthreads();

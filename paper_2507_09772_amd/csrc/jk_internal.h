@@ -148,6 +148,7 @@ struct jk_plan {
     int32_t *d_list = nullptr, *d_list_cnt = nullptr;  // mixed split
     int32_t *d_tpos = nullptr;                         // shell -> index within its type
     bool last_mixed = false;
+    double dscreen = 0.0;  // density screening threshold for later builds (0: off)
     bool no_row = false;  // JK_NO_ROW=1 in the environment: tiles only (A/B measurements)
     float *d_dmax = nullptr;
     Tables tab{};

@@ -71,6 +71,7 @@ def lib():
         L.jk_batch_destroy.argtypes = [vp]
         L.jk_batch_destroy.restype = None
         L.jk_plan_profile.argtypes = [vp, i32]
+        L.jk_plan_set_density_screening.argtypes = [vp, f64]
         L.jk_plan_timings.argtypes = [vp, ctypes.POINTER(ClassTiming), i32, ctypes.POINTER(i32)]
         L.jk_tune_set.argtypes = [i32, i32, i32, i32, i32, i32]
         L.jk_tune_get.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -170,6 +171,11 @@ class Plan:
         if squeeze:
             return (J[0] if J is not None else None), (K[0] if K is not None else None)
         return J, K
+
+    def set_density_screening(self, threshold: float):
+        """Drop quartets with Q_IJ Q_KL max|D_block| below threshold in later
+        builds (0 turns it off)."""
+        _check(lib().jk_plan_set_density_screening(self.h, threshold))
 
     def profile(self, enable: bool = True):
         """Per-kernel HIP-event timing of later executes (resets totals)."""

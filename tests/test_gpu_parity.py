@@ -187,6 +187,38 @@ def test_range_separated(jkmod, torch_cuda, basis, nw, omega):
 
 
 # ---------------------------------------------------------------------------
+# density screening (incremental SCF)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("basis,nw,thr", [("A", 4, 1e-7), ("B", 3, 1e-6), ("A", 8, 1e-8), ("B", 6, 1e-7)])
+def test_density_screening(jkmod, torch_cuda, basis, nw, thr):
+    import torch
+    wl = synth.small_workload(nw, basis, seed=120 + nw)
+    say("density screening", basis, nw, thr)
+    J0, K0, n0 = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, dscreen=thr)
+    plan = jkmod.Plan(wl.mol, wl.cutoff)
+    plan.set_density_screening(thr)
+    _, J, K = run_gpu(jkmod, torch_cuda, wl, plan=plan)
+    assert np.abs(J - J0).max() <= TOL and np.abs(K - K0).max() <= TOL
+    # incremental step: J(D) unscreened, then += J(dD) screened
+    rng = np.random.default_rng(nw)
+    dD = 1e-5 * rng.standard_normal(wl.D.shape)
+    dD = dD + dD.transpose(0, 2, 1)
+    Jd0, Kd0, nd = o.jk(wl.mol, dD, wl.cutoff, mode=1, dscreen=thr)
+    Jf0, Kf0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
+    assert nd < n0
+    plan.set_density_screening(0.0)
+    Dt = torch.from_numpy(wl.D).cuda()
+    Jt, Kt = plan.execute(Dt)
+    plan.set_density_screening(thr)
+    plan.execute(torch.from_numpy(dD).cuda(), J=Jt, K=Kt, flags=jkmod.JK_DO_J | jkmod.JK_DO_K | jkmod.JK_ACCUMULATE)
+    torch.cuda.synchronize()
+    assert np.abs(Jt.cpu().numpy() - (Jf0 + Jd0)).max() <= TOL
+    assert np.abs(Kt.cpu().numpy() - (Kf0 + Kd0)).max() <= TOL
+    with pytest.raises(jkmod.JKError):
+        plan.set_density_screening(-1.0)
+
+
+# ---------------------------------------------------------------------------
 # mixed precision
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("basis,nw", [("A", 4), ("B", 4), ("A", 8)])
@@ -252,6 +284,7 @@ def test_forced_families(jkmod, torch_cuda, basis, nw):
     J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
     ej0, ek0 = o.energies(wl.D, J0, K0)
     Js0, Ks0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, omega=-0.4)
+    Jd0, Kd0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, dscreen=1e-7)
     try:
         for fam in (1, 2):
             for row in (1, 2):
@@ -261,6 +294,10 @@ def test_forced_families(jkmod, torch_cuda, basis, nw):
                     jkmod.tune_set_row(*c, "fp64", row)
                 _, Js, Ks = run_gpu(jkmod, torch_cuda, wl, omega=-0.4)
                 assert np.abs(Js - Js0).max() <= TOL and np.abs(Ks - Ks0).max() <= TOL, ("short range", fam, row)
+                plan = jkmod.Plan(wl.mol, wl.cutoff)
+                plan.set_density_screening(1e-7)
+                _, Jd, Kd = run_gpu(jkmod, torch_cuda, wl, plan=plan)
+                assert np.abs(Jd - Jd0).max() <= TOL and np.abs(Kd - Kd0).max() <= TOL, ("screened", fam, row)
                 for prec in ("fp64", "mixed"):
                     for c in jkmod.canonical_classes():
                         for p in ("fp64", "fp32"):
