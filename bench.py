@@ -199,6 +199,92 @@ def bench_batch(args, torch, jk, synth):
     return res
 
 
+def bench_dscreen(args, torch, plan, wl, dt_full):
+    """Incremental build as in a late direct-SCF iteration: the density
+    change dD = 1e-4 * (a fresh seeded density - D) with density screening
+    at --dscreen; reports its time against the full build, and its error
+    against the same dD built unscreened."""
+    import numpy as np
+    from paper_2507_09772_amd import synth
+    nocc = int(np.rint(np.trace(wl.D[0])))  # D = C C^T with orthonormal C
+    D2 = synth.random_density(wl.mol.nao, nocc, [999, 1], wl.D.shape[0])
+    dD = torch.from_numpy(1e-4 * (D2 - wl.D)).cuda()
+    J = torch.empty_like(dD)
+    K = torch.empty_like(dD)
+    plan.set_density_screening(0.0)
+    plan.execute(dD, J, K)
+    torch.cuda.synchronize()
+    J0, K0 = J.cpu().numpy(), K.cpu().numpy()
+    plan.set_density_screening(args.dscreen)
+    for _ in range(max(args.warmup, 1)):
+        plan.execute(dD, J, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.execute(dD, J, K)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    plan.set_density_screening(0.0)
+    err_j = float(np.abs(J.cpu().numpy() - J0).max())
+    err_k = float(np.abs(K.cpu().numpy() - K0).max())
+    log(f"incremental (dD ~ 1e-4, dscreen {args.dscreen:g}): {dt * 1e3:.2f} ms/build, max|dJ| {err_j:.1e} "
+        f"max|dK| {err_k:.1e} vs unscreened")
+    return {"threshold": args.dscreen, "delta_D": "1e-4 * (seeded density - D)", "ms_per_step": dt * 1e3,
+            "builds_per_s": 1.0 / dt, "speedup_vs_full_build": dt_full / dt,
+            "max_dJ_vs_unscreened": err_j, "max_dK_vs_unscreened": err_k}
+
+
+def bench_micro(args, torch, jk, synth):
+    """Micro-benchmarks after the paper's appendix B, on the c1 / c2
+    geometries with one uniform shell per atom:
+      * (ss|ss) with 1..8 identical primitives per shell (the same contracted
+        function, so the same quartets): FP64 and FP32 time and their ratio;
+      * (dd|dd) and (ff|ff) with 1..4 densities: time against the number of
+        densities, fitted to integral generation + per-density contraction."""
+    import numpy as np
+    out = {"ssss_nprim": [], "ndm": {}}
+    ref = None
+    for npr in range(1, 9):
+        wl = synth.uniform_shell_workload("c1", 0, npr, 0.2700058226)
+        plan = jk.Plan(wl.mol, wl.cutoff)
+        D = torch.from_numpy(wl.D).cuda()
+        J = torch.empty_like(D)
+        K = torch.empty_like(D)
+        row = {"nprim": npr, "nquartets": plan.stats().nquartets}
+        for prec in ("fp64", "fp32"):
+            dt, _ = timed_steps(plan, D, J, K, prec, args.steps, args.warmup, torch)
+            row[prec + "_ms"] = dt * 1e3
+            if prec == "fp64":
+                Jh = J.cpu().numpy()
+                ref = Jh if ref is None else ref
+                row["max_dJ_vs_nprim1"] = float(np.abs(Jh - ref).max())
+        row["fp32_speedup"] = row["fp64_ms"] / row["fp32_ms"]
+        log(f"(ss|ss) nprim {npr}: fp64 {row['fp64_ms']:.3f} ms  fp32 {row['fp32_ms']:.3f} ms  "
+            f"ratio {row['fp32_speedup']:.2f}  (|dJ| vs nprim 1: {row['max_dJ_vs_nprim1']:.1e})")
+        out["ssss_nprim"].append(row)
+        plan.close()
+    for l, lab in ((2, "dddd"), (3, "ffff")):
+        wl = synth.uniform_shell_workload("c2", l, 1, 1.2700058226, nset=4)
+        plan = jk.Plan(wl.mol, wl.cutoff)
+        ts = []
+        J1 = None
+        for n in range(1, 5):
+            D = torch.from_numpy(np.ascontiguousarray(wl.D[:n])).cuda()
+            J = torch.empty_like(D)
+            K = torch.empty_like(D)
+            dt, _ = timed_steps(plan, D, J, K, "fp64", args.steps, args.warmup, torch)
+            ts.append(dt * 1e3)
+            if n == 1:
+                J1 = J[0].cpu().numpy()
+            dj = float(np.abs(J[0].cpu().numpy() - J1).max())
+            log(f"({lab[:2]}|{lab[2:]}) ndm {n}: {dt * 1e3:.2f} ms (|dJ[0]| vs ndm 1: {dj:.1e})")
+        slope, icpt = np.polyfit(np.arange(1, 5), ts, 1)
+        out["ndm"][lab] = {"ms": ts, "integral_ms": float(icpt), "per_density_ms": float(slope),
+                           "nquartets": plan.stats().nquartets}
+        plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +295,9 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-molecule batched builds")
+    ap.add_argument("--no-dscreen", action="store_true", help="skip the incremental (density-screened) build")
+    ap.add_argument("--micro", action="store_true", help="only the appendix-B style micro-benchmarks")
+    ap.add_argument("--dscreen", type=float, default=1e-10, help="density screening threshold")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mix-threshold", type=float, default=1e-4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -235,6 +324,9 @@ def main():
         return
 
     torch.cuda.set_device(0)
+    if args.micro:
+        print(json.dumps({"micro": bench_micro(args, torch, jk, synth)}), flush=True)
+        return
     if args.workload == "c4":
         res = bench_batch(args, torch, jk, synth)
         r64 = res["fp64"]
@@ -304,6 +396,8 @@ def main():
                         "max_dJ_vs_fp64_gpu": float(np.abs(Jm - J64).max()),
                         "max_dK_vs_fp64_gpu": float(np.abs(Km - K64).max()),
                         "threshold": args.mix_threshold}
+    if not args.no_dscreen:
+        out["density_screening"] = bench_dscreen(args, torch, plan, wl, dt64)
     if not args.no_batch:
         out["batch"] = bench_batch(args, torch, jk, synth)
     if not args.no_cpu_baseline:

@@ -275,3 +275,23 @@ def batch_workload(nmol: int = 256, nset: int = 4, seed: int = BATCH_SEED) -> li
         D = random_density(mol.nao, OCC_PER_WATER * int(sizes[m]), [BATCH_DENS_SEED, m], nset)
         out.append(Workload(name=f"b{m}", mol=mol, D=D))
     return out
+
+
+def uniform_shell_workload(name: str, l: int, nprim: int, exponent: float, nset: int = 1,
+                           spherical: bool = False) -> Workload:
+    """Every atom of a single-molecule workload's geometry (c1 or c2) gets
+    the same one shell: angular momentum ``l`` with ``nprim`` copies of one
+    exponent, each weighted 1/nprim, so the contracted function (and hence
+    every integral and the screening) is the same for every ``nprim`` while
+    the primitive work grows as nprim^4 -- the profiling basis of the
+    paper's appendix B micro-benchmarks.  Densities: seeded independently of
+    nprim, nset of them, half as many occupied orbitals as atoms."""
+    spec = WORKLOADS[name]
+    elems, xyz = water_lattice(spec["nwater"], spec["geom_seed"])
+    e = np.full(nprim, float(exponent))
+    c = _contract_norm(e, np.full(nprim, 1.0 / nprim), l)
+    shell = (l, e, c)
+    tmpl = BasisTemplate(name=f"uniform-l{l}", spherical=spherical, shells={"O": [shell], "H": [shell]})
+    mol = build_molecule(tmpl, elems, xyz)
+    D = random_density(mol.nao, max(1, len(elems) // 2), [spec["dens_seed"], l], nset)
+    return Workload(name=f"{name}-l{l}-p{nprim}", mol=mol, D=D)
