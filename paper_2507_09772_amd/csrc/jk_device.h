@@ -395,6 +395,32 @@ struct PQuart {
 template <typename R>
 __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const PrimPair &pk) {
     PQuart<R> g;
+    if constexpr (sizeof(R) == 4) {
+        // single precision quartets: only the centre differences and the
+        // prefactor's product of pair factors are formed in FP64
+        const float p = (float)pb.p, q = (float)pk.p;
+        const float rs = __builtin_amdgcn_rsqf(p + q);
+        const float rpq = rs * rs;
+        float pq2 = 0.0f;
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            const float d = (float)(pb.P[x] - pk.P[x]);
+            g.PQ[x] = d;
+            pq2 += d * d;
+            g.PA[x] = (float)pb.PA[x];
+            g.QC[x] = (float)pk.PA[x];
+        }
+        const float rho = p * q * rpq;
+        g.rho = (double)rho;
+        g.T = (double)(rho * pq2);
+        g.rpq = rpq;
+        g.fq = q * rpq;
+        g.fp = p * rpq;
+        g.pref = (float)(TWO_PI_2_5 * pb.kp * pk.kp) * rs;
+        g.hb = (float)pb.h;
+        g.hk = (float)pk.h;
+        return g;
+    }
     const double p = pb.p, q = pk.p;
     const double rs = rsq64(p + q);
     const double rpq = rs * rs;
