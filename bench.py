@@ -167,17 +167,22 @@ def bench_batch(args, torch, jk, synth):
     nset = Ds[0].shape[0]
     nq = sum(p.stats().nquartets for p in plans)
     res = {"config": BATCH_TEXT, "nmol": len(wls), "nset": nset, "plan_seconds": t_plan, "nquartets": nq}
-    for precision in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+    log(f"batch: {len(wls)} plans in {t_plan:.1f} s, {nq} quartets")
+    # mixed batches only on request: their FP64 list pass is slow for small
+    # molecules (most quartets are above the threshold)
+    for precision in ("fp64",) + (("mixed",) if args.batch_mixed else ()):
         b = jk.Batch(plans, nset=nset, precision=precision, mix_threshold=args.mix_threshold)
         for _ in range(max(args.warmup, 1)):
             b.execute(Ds, Js, Ks)
         torch.cuda.synchronize()
+        log(f"batch {precision}: warm")
         t0 = time.perf_counter()
         for _ in range(args.steps):
             b.execute(Ds, Js, Ks)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
         e = [2.0 * float(np.sum(w.D * J.cpu().numpy())) for w, J in zip(wls, Js)]
+        log(f"batch {precision}: {dt * 1e3:.1f} ms per batch; now one jk_execute per molecule")
         # the same molecules one jk_execute each
         for p, D, J, K in zip(plans, Ds, Js, Ks):
             p.execute(D, J, K, precision=precision)
@@ -297,6 +302,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-molecule batched builds")
     ap.add_argument("--no-dscreen", action="store_true", help="skip the incremental (density-screened) build")
     ap.add_argument("--micro", action="store_true", help="only the appendix-B style micro-benchmarks")
+    ap.add_argument("--batch-mixed", action="store_true", help="also time mixed-precision batches")
     ap.add_argument("--dscreen", type=float, default=1e-10, help="density screening threshold")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mix-threshold", type=float, default=1e-4)

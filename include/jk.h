@@ -222,9 +222,11 @@ int jk_plan_timings(const jk_plan *plan, jk_class_timing *out, int32_t cap, int3
  * LDS.  jk_tune_set picks the family for one class and precision (JK_FP64
  * or JK_FP32; family 0 restores the built-in default); plans read the table
  * when they are created.  jk_tune_set_row controls row mode for one class
- * and precision (0 default = allowed, 1 allowed, 2 off): in row mode a
- * workgroup walks a whole long ket prefix of one bra and keeps the bra's K
- * rows in LDS, so most J/K updates stay out of global atomics.  At load time
+ * and precision (0 default = 1; 1 bras with long ket prefixes; 2 off; 3 every
+ * bra, the short ones in 64-lane workgroups): in row mode a workgroup walks
+ * (a chunk of) one bra's ket prefix and keeps the bra's K rows in LDS, so
+ * most J/K updates stay out of global atomics; batched builds run every bra
+ * of a class as 64-lane row tasks unless its setting is 2.  At load time
  * the library reads tune_gfx950.txt next to itself (or the file named by
  * JK_TUNE_DB): one "li lj lk ll precision family [row]" line per entry,
  * '#' comments.

@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 OUT = os.path.join(HERE, "tune_gfx950.txt")
+ROWNAME = {1: "row", 2: "tile", 3: "allrow"}
 
 
 def measure(jk, synth, torch, names, precision, family, row, steps=2):
@@ -57,10 +58,10 @@ def main():
     from paper_2507_09772_amd import jk, synth
     lines = ["# kernel family per (class, precision), chosen by paper_2507_09772_amd/autotune.py",
              f"# workloads: {' '.join(args.workloads)}; columns: li lj lk ll precision(0 fp64, 2 fp32) family "
-             "row(1 on, 2 off)"]
+             "row(1 long bras, 2 off, 3 all bras)"]
     report = {}
     for precision in ("fp64", "fp32"):
-        t = {(f, r): measure(jk, synth, torch, args.workloads, precision, f, r) for f in (1, 2) for r in (1, 2)}
+        t = {(f, r): measure(jk, synth, torch, args.workloads, precision, f, r) for f in (1, 2) for r in (1, 2, 3)}
         for c in jk.canonical_classes():
             _, avail = jk.tune_get(*c, precision)
             opts = {k: v.get(c) for k, v in t.items() if avail & k[0] and v.get(c) is not None}
@@ -70,8 +71,8 @@ def main():
             report[f"{precision} ({c[0]}{c[1]}|{c[2]}{c[3]})"] = {f"f{k[0]}r{k[1]}": v for k, v in opts.items()}
             lines.append(f"{c[0]} {c[1]} {c[2]} {c[3]} {jk.PRECISION[precision]} {fam} {row}")
             print(f"{precision} ({c[0]}{c[1]}|{c[2]}{c[3]}): " +
-                  "  ".join(f"f{k[0]}/{'row' if k[1] == 1 else 'tile'} {v:8.3f}" for k, v in sorted(opts.items())) +
-                  f"  -> family {fam} {'row' if row == 1 else 'tiles'}", flush=True)
+                  "  ".join(f"f{k[0]}/{ROWNAME[k[1]]} {v:8.3f}" for k, v in sorted(opts.items())) +
+                  f"  -> family {fam} {ROWNAME[row]}", flush=True)
         for c in jk.canonical_classes():
             jk.tune_set(*c, precision, 0)
             jk.tune_set_row(*c, precision, 0)

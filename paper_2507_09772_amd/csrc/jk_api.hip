@@ -450,6 +450,7 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 if (!avail[f - 1]) f = 3 - f;
                 c.fam[pr] = f;
                 c.row_ok[pr] = g_row[class_id(c.li, c.lj, c.lk, c.ll)][pr] != 2;
+                c.row_short[pr] = g_row[class_id(c.li, c.lj, c.lk, c.ll)][pr] == 3;
             }
             std::vector<int32_t> bl, cn, to[2];
             const auto &kq = sortedq[kt];
@@ -504,6 +505,10 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                         c.nq_row += cn[i];
                         continue;
                     }
+                    // short bra: one 64-lane row task over all its kets
+                    c.h_srowt.push_back((int32_t)i);
+                    c.h_srowt.push_back(0);
+                    c.h_srowt.push_back(cn[i]);
                     sb.push_back(bl[i]);
                     scn.push_back(cn[i]);
                     for (int f = 0; f < 2; ++f) {
@@ -531,6 +536,7 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                         }
                         c.nrowc[f] = (int)(tasks.size() / 3);
                         if ((rc = P->put(&c.d_rowc[f], tasks))) return rc;
+                        c.h_rowc[f] = tasks;
                     }
                     if (c.nsbra > 0) {
                         if ((rc = P->put(&c.d_sbra, sb)) || (rc = P->put(&c.d_scnt, scn))) return rc;
@@ -543,6 +549,8 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                     c.nrow = 0;
                     c.nq_row = 0;
                 }
+                c.nsrow = (int)(c.h_srowt.size() / 3);
+                if (c.nsrow > 0 && (ce.srow[0][0] || ce.srow[1][0]) && (rc = P->put(&c.d_srowt, c.h_srowt))) return rc;
             }
             nq_tot += c.nq;
             npq_tot += c.npq;
@@ -622,7 +630,8 @@ static int tune_set_impl(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t
 static int tune_set_row_impl(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t row) {
     if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
     if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
-    if (row < 0 || row > 2) return fail(JK_EINVAL, "row must be 0 (default), 1 (allowed) or 2 (off)");
+    if (row < 0 || row > 3)
+        return fail(JK_EINVAL, "row must be 0 (default), 1 (long bras), 2 (off) or 3 (long and short bras)");
     g_row[class_id(li, lj, lk, ll)][precision == JK_FP32 ? 1 : 0] = row;
     return 0;
 }
@@ -827,22 +836,36 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
         a.list_count = P->d_list_cnt ? P->d_list_cnt + ci : nullptr;
         a.nq = (int32_t)c.nq;
         const int slot = (int)(2 * ci + pr) * 3;  // + kind
-        const size_t row_lds =
-            row_lds_bytes(e, f, pr, c.li, c.lj, nset, c.ncolK + (c.seg_same ? 0 : c.ncolL));
-        const bool rowmode = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] && row_lds <= (size_t)ROW_LDS_MAX && !P->no_row;
-        if (rowmode) {
-            // long bras: one workgroup each; the short rest as tiles
+        const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
+        const bool longrows = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
+                              row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4) <= (size_t)ROW_LDS_MAX && !P->no_row;
+        const bool shortrows = c.row_short[pr] && c.nsrow > 0 && e.srow[f - 1][pr] && (longrows || c.nrow == 0) &&
+                               row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 1) <= (size_t)ROW_LDS_MAX && !P->no_row;
+        if (longrows || shortrows) {
             a.bra_list = c.d_bra;
             a.bra_cnt = c.d_cnt;
-            a.row_pos = c.d_rowc[f - 1];
-            a.nrow = c.nrowc[f - 1];
             a.tshK = c.d_tshK;
             a.tshL = c.d_tshL;
             a.ncolK = c.ncolK;
             a.ncolL = c.ncolL;
             a.seg_same = c.seg_same;
+        }
+        if (longrows) {
+            // long bras: 256-lane workgroups over chunks of their kets
+            a.row_pos = c.d_rowc[f - 1];
+            a.nrow = c.nrowc[f - 1];
             if ((rc = mark(slot + 1, c.nq_row))) return rc;
             HIPCHK(e.row[f - 1][pr](a, s));
+        }
+        if (shortrows) {
+            // short bras: one 64-lane workgroup each
+            a.row_pos = c.d_srowt;
+            a.nrow = c.nsrow;
+            if ((rc = mark(slot + 1, c.nq - c.nq_row))) return rc;
+            HIPCHK(e.srow[f - 1][pr](a, s));
+            a.ntiles = 0;
+        } else if (longrows) {
+            // the short rest as tiles
             a.bra_list = c.d_sbra;
             a.bra_cnt = c.d_scnt;
             a.nbra = c.nsbra;
@@ -856,7 +879,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
             a.ntiles = c.ntiles[f - 1];
         }
         if (a.ntiles > 0) {
-            if ((rc = mark(slot, rowmode ? c.nq - c.nq_row : c.nq))) return rc;
+            if ((rc = mark(slot, longrows ? c.nq - c.nq_row : c.nq))) return rc;
             HIPCHK(e.tiles[f - 1][pr](a, s));
         }
         if (precision == JK_MIXED) {

@@ -68,6 +68,8 @@ __global__ void kb_zero_i32(int32_t *p, int n) {
 // group.
 struct Group {
     int cid, fam, fam64;
+    int kind;          // 0: tiles, 1: 64-lane row tasks
+    size_t lds;        // row tasks: largest dynamic LDS over the descriptors
     int first, count;
     int total_tiles;
     int64_t list_cap;  // mixed: summed list capacity of the descriptors
@@ -86,6 +88,7 @@ struct jk_batch {
     BatchDesc *d_desc = nullptr;
     std::vector<Group> groups;
     int32_t *d_ctr = nullptr;  // mixed split: list counts per (molecule, class)
+    int32_t *d_tasks = nullptr;  // row tasks of the row-kind descriptors
     int nctr = 0;
     int64_t max_elems = 0;      // largest nset * naoc^2 over the molecules
     int max_ns2 = 0;
@@ -134,7 +137,8 @@ static int record(jk_batch *b) {
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const Group &g = b->groups[gi];
         const ClassEntry &e = g_classes[g.cid];
-        HIPCHK(e.batch[g.fam - 1][pr](b->d_desc + g.first, g.count, g.total_tiles, s));
+        if (g.kind == 1) HIPCHK(e.batch_row[g.fam - 1][pr](b->d_desc + g.first, g.count, g.total_tiles, g.lds, s));
+        else HIPCHK(e.batch[g.fam - 1][pr](b->d_desc + g.first, g.count, g.total_tiles, s));
         if (b->precision == JK_MIXED) HIPCHK(e.batch_list[g.fam64 - 1](b->d_desc + g.first, g.count, g.list_cap, s));
     }
     hipLaunchKernelGGL(kb_finalize, dim3(grid_rows(b->max_elems), nm), dim3(256), 0, s, b->d_mol, b->nset);
@@ -186,9 +190,14 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         return rc;
     if (precision == JK_MIXED && ((rc = b->alloc(&dmax, soff[nmol])) || (rc = b->alloc(&list, loff[nmol])))) return rc;
 
-    // descriptors grouped by (class, family); heavy molecules first
+    // descriptors grouped by (class, family, kind); heavy molecules first.
+    // Unless row mode is off for the class, every bra runs as 64-lane row
+    // tasks (K rows in LDS): the small molecules of a batch have few long
+    // bras, and per-quartet K atomics would dominate.
     const int pr = precision == JK_FP64 ? 0 : 1;
-    std::map<std::tuple<int, int, int>, std::vector<std::pair<double, BatchDesc>>> byg;
+    std::map<std::tuple<int, int, int, int>, std::vector<std::pair<double, BatchDesc>>> byg;
+    std::vector<int32_t> alltasks;
+    std::map<std::tuple<int, int, int, int>, size_t> glds;
     b->hmol.resize(nmol);
     for (int m = 0; m < nmol; ++m) {
         const jk_plan *P = plans[m];
@@ -208,6 +217,10 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             const ClassTask &c = P->cls[ci];
             const int f = c.fam[pr];
             if (c.ntiles[f - 1] <= 0) continue;
+            const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
+            const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
+            const size_t lds1 = row_lds_bytes(ce, f, pr, c.li, c.lj, nset, ncols, 1);
+            const int kind = c.row_ok[pr] && ce.batch_row[f - 1][pr] && lds1 <= (size_t)ROW_LDS_MAX ? 1 : 0;
             BatchDesc d{};
             JkArgs &a = d.a;
             a.pairs = P->d_pairs;
@@ -240,10 +253,27 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             a.mix_thr = mix_threshold;
             a.tab = P->tab;
             d.pad[0] = (int32_t)(coff[m] + (int64_t)ci);  // list counter slot (host only)
-            const ClassEntry &e = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
-            if (!e.batch[f - 1][pr] || (precision == JK_MIXED && !e.batch_list[c.fam[0] - 1]))
+            d.pad[1] = a.ntiles;                           // work units (tiles or row tasks)
+            if (kind == 1) {
+                // every bra of the class: long bras in chunks, short ones whole
+                const size_t first = alltasks.size();
+                alltasks.insert(alltasks.end(), c.h_rowc[f - 1].begin(), c.h_rowc[f - 1].end());
+                alltasks.insert(alltasks.end(), c.h_srowt.begin(), c.h_srowt.end());
+                d.pad[1] = (int32_t)((alltasks.size() - first) / 3);
+                d.pad[2] = (int32_t)first;                 // offset into the task buffer (host only)
+                a.nrow = d.pad[1];
+                a.tshK = c.d_tshK;
+                a.tshL = c.d_tshL;
+                a.ncolK = c.ncolK;
+                a.ncolL = c.ncolL;
+                a.seg_same = c.seg_same;
+                if (alltasks.size() > (size_t)INT32_MAX) return fail(JK_EINVAL, "too many row tasks");
+            }
+            if (!(kind == 1 || ce.batch[f - 1][pr]) || (precision == JK_MIXED && !ce.batch_list[c.fam[0] - 1]))
                 return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has no batched kernel", c.li, c.lj, c.lk, c.ll);
-            byg[{class_id(c.li, c.lj, c.lk, c.ll), f, c.fam[0]}].push_back({c.flops, d});
+            const auto key = std::make_tuple(class_id(c.li, c.lj, c.lk, c.ll), f, c.fam[0], kind);
+            byg[key].push_back({c.flops, d});
+            if (kind == 1) glds[key] = std::max(glds[key], lds1);
         }
     }
     for (auto &kv : byg) {
@@ -253,12 +283,14 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         g.cid = std::get<0>(kv.first);
         g.fam = std::get<1>(kv.first);
         g.fam64 = std::get<2>(kv.first);
+        g.kind = std::get<3>(kv.first);
+        g.lds = g.kind == 1 ? glds[kv.first] : 0;
         g.first = (int)b->hdesc.size();
         g.count = (int)v.size();
         int64_t tiles = 0;
         for (auto &x : v) {
             x.second.tile_base = (int32_t)tiles;
-            tiles += x.second.a.ntiles;
+            tiles += x.second.pad[1];
             g.list_cap += x.second.a.nq;
             g.work += x.first;
             b->hdesc.push_back(x.second);
@@ -268,12 +300,22 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         b->groups.push_back(g);
     }
     std::stable_sort(b->groups.begin(), b->groups.end(), [](const Group &x, const Group &y) { return x.work > y.work; });
-    // one list count per (molecule, class)
+    // one list count per (molecule, class); row tasks to the device
     b->nctr = (int)coff[nmol];
     if ((rc = b->alloc(&b->d_ctr, b->nctr))) return rc;
+    if ((rc = b->alloc(&b->d_tasks, alltasks.size()))) return rc;
+    if (!alltasks.empty())
+        HIPCHK(hipMemcpy(b->d_tasks, alltasks.data(), sizeof(int32_t) * alltasks.size(), hipMemcpyHostToDevice));
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const Group &g = b->groups[gi];
+        for (int k = 0; k < g.count; ++k) {
+            BatchDesc &d = b->hdesc[g.first + k];
+            if (g.kind == 1) d.a.row_pos = b->d_tasks + d.pad[2];
+        }
+    }
     for (BatchDesc &d : b->hdesc) {
         d.a.list_count = precision == JK_MIXED ? b->d_ctr + d.pad[0] : nullptr;
-        d.pad[0] = 0;
+        d.pad[0] = d.pad[1] = d.pad[2] = 0;
     }
     if ((rc = b->alloc(&b->d_desc, b->hdesc.size())) || (rc = b->alloc(&b->d_mol, nmol))) return rc;
     if (!b->hdesc.empty())

@@ -694,28 +694,46 @@ __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
     }
 }
 
-// Row mode: one workgroup of 256 lanes walks the whole ket prefix of one bra.
-// K'_IK, K'_IL (row block of shell I) and K'_JK, K'_JL (row block of J)
-// accumulate in LDS over the compressed ket-type columns, J'_IJ in LDS, and
-// only J'_KL goes to global atomics per quartet.  Dynamic LDS layout, per
-// density: [NI rows | NJ rows] x ncols, then NAB for J'_IJ.
-template <int LI, int LJ, int LK, int LL, typename R>
-__global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
+struct BatchDesc {
+    JkArgs a;
+    int32_t tile_base;
+    int32_t pad[3];
+};
+
+__device__ __forceinline__ int batch_desc(const BatchDesc *__restrict__ d, int n, int g) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].tile_base <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Row mode: one workgroup of NT lanes walks a chunk of one bra's ket prefix
+// (a row task: list position, first and end ket).  K'_IK, K'_IL (row block
+// of shell I) and K'_JK, K'_JL (row block of J) accumulate in LDS over the
+// compressed ket-type columns, J'_IJ in LDS, and only J'_KL goes to global
+// atomics per quartet.  Dynamic LDS layout, per density: [NI rows | NJ rows]
+// x ncols, then NAB for J'_IJ.  NT = 256 for long bras, 64 for short ones;
+// BATCH: the task indexes the row tasks of many descriptors (molecules).
+template <int LI, int LJ, int LK, int LL, typename R, int NT>
+__device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
     using C = Cls<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NAB = C::NAB, NCD = C::NCD;
     extern __shared__ double rowmem[];
     const int tid = threadIdx.x, lane = lane_index();
-    const int i = a.row_pos[3 * blockIdx.x];
-    const int jbeg = a.row_pos[3 * blockIdx.x + 1], cnt = a.row_pos[3 * blockIdx.x + 2];
+    const int i = a.row_pos[3 * task];
+    const int jbeg = a.row_pos[3 * task + 1], cnt = a.row_pos[3 * task + 2];
     const int bra = a.bra_list[i];
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
     const int segL = a.seg_same ? 0 : a.ncolK;
     const int per_set = (NI + NJ) * ncols + NAB;
-    for (int t = tid; t < per_set * a.nset; t += 256) rowmem[t] = 0.0;
+    for (int t = tid; t < per_set * a.nset; t += NT) rowmem[t] = 0.0;
     __syncthreads();
     const PairRec B = a.pairs[bra];
     const int n = a.nao;
-    for (int j0 = jbeg; j0 < cnt; j0 += 256) {
+    for (int j0 = jbeg; j0 < cnt; j0 += NT) {
         const int j = j0 + tid;
         bool valid = j < cnt;
         const int ket = a.ket_list[valid ? j : cnt - 1];
@@ -841,7 +859,7 @@ __global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
         const double *rm = rowmem + s * per_set;
         double *Jm = a.J + s * a.mstride;
         double *Km = a.K + s * a.mstride;
-        for (int t = tid; t < per_set; t += 256) {
+        for (int t = tid; t < per_set; t += NT) {
             const double v = rm[t];
             if (v == 0.0) continue;
             if (t >= (NI + NJ) * ncols) {
@@ -856,6 +874,18 @@ __global__ void __launch_bounds__(256) jk_k1_row(const JkArgs a) {
             else col = a.aoc[a.tshL[(c - a.ncolK) / NL]] + (c - a.ncolK) % NL;
             atomic_add_f64(&Km[row * n + col], v);
         }
+    }
+}
+
+template <int LI, int LJ, int LK, int LL, typename R, int NT, bool BATCH>
+__global__ void __launch_bounds__(NT) jk_k1_row(const JkArgs a, const BatchDesc *__restrict__ descs, int ndesc) {
+    if constexpr (BATCH) {
+        const int g = blockIdx.x;
+        const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
+        const JkArgs d = descs[m].a;
+        k1_row_task<LI, LJ, LK, LL, R, NT>(d, g - descs[m].tile_base);
+    } else {
+        k1_row_task<LI, LJ, LK, LL, R, NT>(a, blockIdx.x);
     }
 }
 
@@ -1164,43 +1194,54 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
 // Row mode for family 2: four independent waves per workgroup walk one bra's
 // ket prefix (interleaved by QW quartets), sharing the bra's K rows and J_IJ
 // in LDS; one workgroup barrier before the final flush.
-// Dynamic LDS: [nset][(NI+NJ) ncols + NI NJ] doubles, then 4 waves x
-// QW x DIG doubles, then 4 waves x QW x TAB reals.
+// Dynamic LDS: [nset][(NI+NJ) ncols + NI NJ] doubles, then (waves) x
+// QW x DIG doubles, then (waves) x QW x TAB reals.
 template <int LI, int LJ, int LK, int LL>
 struct K2RowLds {
     using F = K2Cfg<LI, LJ, LK, LL>;
+    // per wave of the workgroup
     template <typename R>
-    static constexpr size_t fixed() { return 4 * (size_t)F::QW * (F::DIG * sizeof(double) + F::TAB * sizeof(R)); }
+    static constexpr size_t fixed() { return (size_t)F::QW * (F::DIG * sizeof(double) + F::TAB * sizeof(R)); }
     static constexpr size_t per_set(int ncols) {
         return sizeof(double) * ((size_t)(ncart(LI) + ncart(LJ)) * ncols + (size_t)ncart(LI) * ncart(LJ));
     }
 };
 
-template <int LI, int LJ, int LK, int LL, typename R>
-__global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
+// (The body stays in the kernel itself: behind one more inlined function
+// layer hipcc moved the (ff|ff) FP64 accumulators to scratch and the kernel
+// returned wrong values, as with the tile prologue.)
+template <int LI, int LJ, int LK, int LL, typename R, int NT, bool BATCH>
+__global__ void __launch_bounds__(NT) jk_k2_row(const JkArgs a_in, const BatchDesc *__restrict__ descs, int ndesc) {
     using C = Cls<LI, LJ, LK, LL>;
     using F = K2Cfg<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NAB = C::NAB;
-    constexpr int QW = F::QW, LPQ = F::LPQ;
+    constexpr int QW = F::QW, LPQ = F::LPQ, NW = NT / 64;
     extern __shared__ double smem2[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_index();
+    int task = blockIdx.x;
+    JkArgs a = a_in;
+    if constexpr (BATCH) {
+        const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, task));
+        a = descs[m].a;
+        task -= descs[m].tile_base;
+    }
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
     const int segL = a.seg_same ? 0 : a.ncolK;
     const int per_set = (NI + NJ) * ncols + NAB;
     double *rows = smem2;
     double *dig = rows + (size_t)per_set * a.nset + (size_t)wave * QW * F::DIG;
-    R *tabs = (R *)(rows + (size_t)per_set * a.nset + 4 * QW * F::DIG) + (size_t)wave * QW * F::TAB;
-    const int i = a.row_pos[3 * blockIdx.x];
-    const int jbeg = a.row_pos[3 * blockIdx.x + 1], cnt = a.row_pos[3 * blockIdx.x + 2];
+    R *tabs = (R *)(rows + (size_t)per_set * a.nset + NW * QW * F::DIG) + (size_t)wave * QW * F::TAB;
+    const int i = a.row_pos[3 * task];
+    const int jbeg = a.row_pos[3 * task + 1], cnt = a.row_pos[3 * task + 2];
     const int bra = a.bra_list[i];
-    for (int t = tid; t < per_set * a.nset; t += 256) rows[t] = 0.0;
+    for (int t = tid; t < per_set * a.nset; t += NT) rows[t] = 0.0;
     __syncthreads();
     const int q = QW > 1 ? lane / LPQ : 0;
     const int sl = QW > 1 ? lane % LPQ : lane;
     const bool lane_used = q < QW;
     const int qq = lane_used ? q : 0;
     const PairRec &B = a.pairs[bra];
-    for (int j0 = jbeg + wave * QW; j0 < cnt; j0 += 4 * QW) {
+    for (int j0 = jbeg + wave * QW; j0 < cnt; j0 += NW * QW) {
         const int j = j0 + qq;
         bool valid = lane_used && j < cnt;
         const int ket = a.ket_list[j < cnt ? j : cnt - 1];
@@ -1217,7 +1258,7 @@ __global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
         const double *rm = rows + s * per_set;
         double *Jm = a.J + s * a.mstride;
         double *Km = a.K + s * a.mstride;
-        for (int t = tid; t < per_set; t += 256) {
+        for (int t = tid; t < per_set; t += NT) {
             const double v = rm[t];
             if (v == 0.0) continue;
             if (t >= (NI + NJ) * ncols) {
@@ -1235,6 +1276,7 @@ __global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
     }
 }
 
+
 // ===========================================================================
 // Batched builds: one launch per (class, family) covers the tiles of every
 // molecule of the batch.  Global tile g belongs to the descriptor m with
@@ -1242,22 +1284,6 @@ __global__ void __launch_bounds__(256) jk_k2_row(const JkArgs a) {
 // one (molecule, class task), heaviest first, so the dispatcher hands out
 // the long tiles early.
 // ===========================================================================
-struct BatchDesc {
-    JkArgs a;
-    int32_t tile_base;
-    int32_t pad[3];
-};
-
-__device__ __forceinline__ int batch_desc(const BatchDesc *__restrict__ d, int n, int g) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (d[mid].tile_base <= g) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 template <int LI, int LJ, int LK, int LL, typename R>
 __global__ void __launch_bounds__(256) jk_k1_batch(const BatchDesc *__restrict__ descs, int ndesc, int total) {
     const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));

@@ -118,11 +118,16 @@ struct ClassTask {
     int64_t nq_row = 0;  // quartets of the long bras
     int nrowc[2] = {0, 0};                       // row tasks per family
     int32_t *d_rowc[2] = {nullptr, nullptr};     // (list position, ket begin, ket end) per task
+    std::vector<int32_t> h_rowc[2];              // host copies (batched builds)
+    int nsrow = 0;                               // short bras as 64-lane row tasks
+    int32_t *d_srowt = nullptr;
+    std::vector<int32_t> h_srowt;
     int32_t *d_sbra = nullptr, *d_scnt = nullptr, *d_stile[2] = {nullptr, nullptr};
     int ncolK = 0, ncolL = 0, seg_same = 0;
     const int32_t *d_tshK = nullptr, *d_tshL = nullptr;
     int fam[2];          // family per precision (0 FP64, 1 FP32)
     bool row_ok[2];      // row mode allowed per precision
+    bool row_short[2];   // short bras in row mode too (64-lane workgroups)
     int ntiles[2];       // per family - 1
     int64_t nq, npq, list_off;
     double flops;

@@ -12,21 +12,24 @@ using Launcher = hipError_t (*)(const JkArgs &, hipStream_t);
 // Batched builds: the tiles of many descriptors (molecules) in one launch.
 using BatchLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int total_tiles, hipStream_t);
 using BatchListLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int64_t nq_total, hipStream_t);
+using BatchRowLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int total_tasks, size_t lds, hipStream_t);
 
 struct ClassEntry {
     Launcher tiles[2][2];  // [family - 1][0: FP64, 1: FP32], quartets from tiles
     Launcher list64[2];    // [family - 1], FP64 pass over the appended list
     Launcher ex64, ex32;   // export (default family)
-    Launcher row[2][2];    // row mode, [family - 1][0: FP64, 1: FP32]
-    size_t row_fixed[2][2];  // row-mode LDS bytes besides the K rows, [family - 1][precision]
+    Launcher row[2][2];    // row mode, 256-lane workgroups (long bras), [family - 1][0: FP64, 1: FP32]
+    Launcher srow[2][2];   // row mode, 64-lane workgroups (short bras)
+    size_t row_fixed[2][2];  // row-mode LDS bytes per wave besides the K rows, [family - 1][precision]
     BatchLauncher batch[2][2];       // [family - 1][precision]
     BatchListLauncher batch_list[2]; // [family - 1], FP64 list pass of the mixed split
+    BatchRowLauncher batch_row[2][2];  // 64-lane row tasks of many descriptors
 };
 
-// LDS bytes of one row-mode workgroup: the fixed part plus nset copies of
-// the bra's K rows over ncols compressed columns and its J_IJ block.
-inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj, int nset, int ncols) {
-    return e.row_fixed[fam - 1][pr] +
+// LDS bytes of one row-mode workgroup of nw waves: the fixed part plus nset
+// copies of the bra's K rows over ncols compressed columns and its J_IJ block.
+inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj, int nset, int ncols, int nw) {
+    return (size_t)nw * e.row_fixed[fam - 1][pr] +
            sizeof(double) * (size_t)nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj));
 }
 

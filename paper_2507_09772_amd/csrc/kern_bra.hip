@@ -21,39 +21,68 @@ static hipError_t launch_k1(const JkArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int LI, int LJ, int LK, int LL, typename R>
+// Dynamic LDS above 64 KB needs a per-kernel opt-in (once per kernel).
+template <typename K>
+static hipError_t lds_opt_in(K kernel, size_t lds, bool &done) {
+    if (lds <= 64 * 1024 || done) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, ROW_LDS_MAX);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+static size_t k1_row_lds(const JkArgs &a, int li, int lj) {
+    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
+    return sizeof(double) * a.nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj));
+}
+
+template <int LI, int LJ, int LK, int LL, typename R, int NT>
 static hipError_t launch_row(const JkArgs &a, hipStream_t s) {
     if (a.nrow <= 0) return hipSuccess;
-    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
-    const size_t lds = sizeof(double) * (size_t)a.nset *
-                       ((size_t)(ncart(LI) + ncart(LJ)) * ncols + (size_t)ncart(LI) * ncart(LJ));
+    const size_t lds = k1_row_lds(a, LI, LJ);
     if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
     static bool opted_in = false;
-    if (lds > 64 * 1024 && !opted_in) {
-        const hipError_t e = hipFuncSetAttribute((const void *)&jk_k1_row<LI, LJ, LK, LL, R>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, ROW_LDS_MAX);
-        if (e != hipSuccess) return e;
-        opted_in = true;
-    }
-    hipLaunchKernelGGL((jk_k1_row<LI, LJ, LK, LL, R>), dim3(a.nrow), dim3(256), lds, s, a);
+    const hipError_t e = lds_opt_in(&jk_k1_row<LI, LJ, LK, LL, R, NT, false>, lds, opted_in);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((jk_k1_row<LI, LJ, LK, LL, R, NT, false>), dim3(a.nrow), dim3(NT), lds, s, a,
+                       (const BatchDesc *)nullptr, 0);
     return hipGetLastError();
 }
 
-template <int LI, int LJ, int LK, int LL, typename R>
+template <int LI, int LJ, int LK, int LL, typename R, int NT>
 static hipError_t launch_row2(const JkArgs &a, hipStream_t s) {
     if (a.nrow <= 0) return hipSuccess;
     using L = K2RowLds<LI, LJ, LK, LL>;
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
-    const size_t lds = L::template fixed<R>() + (size_t)a.nset * L::per_set(ncols);
+    const size_t lds = (NT / 64) * L::template fixed<R>() + (size_t)a.nset * L::per_set(ncols);
     if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
     static bool opted_in = false;
-    if (lds > 64 * 1024 && !opted_in) {
-        const hipError_t e = hipFuncSetAttribute((const void *)&jk_k2_row<LI, LJ, LK, LL, R>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, ROW_LDS_MAX);
-        if (e != hipSuccess) return e;
-        opted_in = true;
-    }
-    hipLaunchKernelGGL((jk_k2_row<LI, LJ, LK, LL, R>), dim3(a.nrow), dim3(256), lds, s, a);
+    const hipError_t e = lds_opt_in(&jk_k2_row<LI, LJ, LK, LL, R, NT, false>, lds, opted_in);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((jk_k2_row<LI, LJ, LK, LL, R, NT, false>), dim3(a.nrow), dim3(NT), lds, s, a,
+                       (const BatchDesc *)nullptr, 0);
+    return hipGetLastError();
+}
+
+// Batched 64-lane row tasks; lds = the largest workgroup need over the descriptors.
+template <int LI, int LJ, int LK, int LL, typename R>
+static hipError_t launch_row_batch(const BatchDesc *d, int ndesc, int total, size_t lds, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
+    static bool opted_in = false;
+    const hipError_t e = lds_opt_in(&jk_k1_row<LI, LJ, LK, LL, R, 64, true>, lds, opted_in);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((jk_k1_row<LI, LJ, LK, LL, R, 64, true>), dim3(total), dim3(64), lds, s, JkArgs{}, d, ndesc);
+    return hipGetLastError();
+}
+
+template <int LI, int LJ, int LK, int LL, typename R>
+static hipError_t launch_row2_batch(const BatchDesc *d, int ndesc, int total, size_t lds, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
+    static bool opted_in = false;
+    const hipError_t e = lds_opt_in(&jk_k2_row<LI, LJ, LK, LL, R, 64, true>, lds, opted_in);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((jk_k2_row<LI, LJ, LK, LL, R, 64, true>), dim3(total), dim3(64), lds, s, JkArgs{}, d, ndesc);
     return hipGetLastError();
 }
 
@@ -110,8 +139,12 @@ static void reg_one() {
             e.tiles[0][0] = &launch_k1<LI, LJ, LK, LL, double, MODE_JK>;
             e.tiles[0][1] = &launch_k1<LI, LJ, LK, LL, float, MODE_JK>;
             e.list64[0] = &launch_k1<LI, LJ, LK, LL, double, MODE_LIST>;
-            e.row[0][0] = &launch_row<LI, LJ, LK, LL, double>;
-            e.row[0][1] = &launch_row<LI, LJ, LK, LL, float>;
+            e.row[0][0] = &launch_row<LI, LJ, LK, LL, double, 256>;
+            e.row[0][1] = &launch_row<LI, LJ, LK, LL, float, 256>;
+            e.srow[0][0] = &launch_row<LI, LJ, LK, LL, double, 64>;
+            e.srow[0][1] = &launch_row<LI, LJ, LK, LL, float, 64>;
+            e.batch_row[0][0] = &launch_row_batch<LI, LJ, LK, LL, double>;
+            e.batch_row[0][1] = &launch_row_batch<LI, LJ, LK, LL, float>;
             e.batch[0][0] = &launch_k1_batch<LI, LJ, LK, LL, double>;
             e.batch[0][1] = &launch_k1_batch<LI, LJ, LK, LL, float>;
             e.batch_list[0] = &launch_k1_batch_list<LI, LJ, LK, LL>;
@@ -120,8 +153,12 @@ static void reg_one() {
             e.tiles[1][0] = &launch_k2<LI, LJ, LK, LL, double, MODE_JK>;
             e.tiles[1][1] = &launch_k2<LI, LJ, LK, LL, float, MODE_JK>;
             e.list64[1] = &launch_k2<LI, LJ, LK, LL, double, MODE_LIST>;
-            e.row[1][0] = &launch_row2<LI, LJ, LK, LL, double>;
-            e.row[1][1] = &launch_row2<LI, LJ, LK, LL, float>;
+            e.row[1][0] = &launch_row2<LI, LJ, LK, LL, double, 256>;
+            e.row[1][1] = &launch_row2<LI, LJ, LK, LL, float, 256>;
+            e.srow[1][0] = &launch_row2<LI, LJ, LK, LL, double, 64>;
+            e.srow[1][1] = &launch_row2<LI, LJ, LK, LL, float, 64>;
+            e.batch_row[1][0] = &launch_row2_batch<LI, LJ, LK, LL, double>;
+            e.batch_row[1][1] = &launch_row2_batch<LI, LJ, LK, LL, float>;
             e.row_fixed[1][0] = K2RowLds<LI, LJ, LK, LL>::template fixed<double>();
             e.row_fixed[1][1] = K2RowLds<LI, LJ, LK, LL>::template fixed<float>();
             e.batch[1][0] = &launch_k2_batch<LI, LJ, LK, LL, double>;

@@ -254,7 +254,9 @@ def tune_set(li, lj, lk, ll, precision, family):
 
 
 def tune_set_row(li, lj, lk, ll, precision, row):
-    """Row mode for one canonical class: 0 default (allowed), 1 allowed, 2 off."""
+    """Row mode for one canonical class: 0 default (= 1), 1 bras with long ket
+    prefixes, 2 off, 3 every bra (short ones in 64-lane workgroups); batched
+    builds run the class as row tasks unless it is 2."""
     _check(lib().jk_tune_set_row(li, lj, lk, ll, PRECISION[precision], row))
 
 

@@ -74,6 +74,45 @@ def test_batch_matches_single_and_replays(env, precision, tol):
     b.close()
 
 
+@pytest.mark.parametrize("fam", [1, 2])
+def test_batch_row_tasks(env, fam):
+    """Every class forced to row mode on all bras (the batch then runs row
+    tasks instead of tiles) and to one family, FP64 and mixed, against the
+    single-molecule builds and the oracle."""
+    torch, jk = env
+    wls = synth.batch_workload(nmol=12, nset=2, seed=13)
+    say("batch rows", fam, [w.mol.nwater for w in wls])
+    try:
+        for c in jk.canonical_classes():
+            for p in ("fp64", "fp32"):
+                _, avail = jk.tune_get(*c, p)
+                jk.tune_set(*c, p, fam if avail & fam else 0)
+                jk.tune_set_row(*c, p, 3)
+        plans, Ds = _setup(torch, jk, wls)
+        for precision, tol in (("fp64", 1e-12), ("mixed", 1e-11)):
+            ref = _singles(torch, plans, Ds, precision)
+            b = jk.Batch(plans, nset=2, precision=precision)
+            Js = [torch.full_like(D, np.nan) for D in Ds]
+            Ks = [torch.full_like(D, np.nan) for D in Ds]
+            for rep in range(2):
+                b.execute(Ds, Js, Ks)
+                torch.cuda.synchronize()
+                for m in range(len(wls)):
+                    assert np.abs(Js[m].cpu().numpy() - ref[m][0]).max() <= tol, (precision, rep, m)
+                    assert np.abs(Ks[m].cpu().numpy() - ref[m][1]).max() <= tol, (precision, rep, m)
+            b.close()
+        for m, w in enumerate(wls):
+            if w.mol.nwater <= 2:
+                J0, K0, _ = o.jk(w.mol, w.D, w.cutoff, mode=1)
+                assert np.abs(ref[m][0] - J0).max() <= 1e-6  # mixed reference vs FP64 oracle
+    finally:
+        for c in jk.canonical_classes():
+            for p in ("fp64", "fp32"):
+                jk.tune_set(*c, p, 0)
+                jk.tune_set_row(*c, p, 0)
+        jk.tune_load(os.path.join(os.path.dirname(jk.__file__), "tune_gfx950.txt"))
+
+
 def test_batch_pointer_change(env):
     torch, jk = env
     wls = synth.batch_workload(nmol=6, nset=1, seed=12)

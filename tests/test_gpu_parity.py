@@ -287,7 +287,7 @@ def test_forced_families(jkmod, torch_cuda, basis, nw):
     Jd0, Kd0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, dscreen=1e-7)
     try:
         for fam in (1, 2):
-            for row in (1, 2):
+            for row in (1, 2, 3):
                 for c in jkmod.canonical_classes():
                     _, avail = jkmod.tune_get(*c, "fp64")
                     jkmod.tune_set(*c, "fp64", fam if avail & fam else 0)
