@@ -106,8 +106,8 @@ def kernel_name(t):
     profiler's kernel name without namespace)."""
     prec = "double" if t.precision == 0 else "float"
     cls = f"{t.li}, {t.lj}, {t.lk}, {t.ll}"
-    if t.kind == 1:
-        return f"jk_k{t.family}_row<{cls}, {prec}>"
+    if t.kind in (1, 3):
+        return f"jk_k{t.family}_row<{cls}, {prec}, {256 if t.kind == 1 else 64}, false>"
     return f"jk_k{t.family}<{cls}, {prec}, {0 if t.kind == 0 else 2}>"
 
 

@@ -205,7 +205,8 @@ typedef struct {
     int32_t precision;          /* JK_FP64 or JK_FP32 */
     int32_t launches;           /* launches summed into ms (one per build) */
     int32_t family;             /* kernel family (1, 2) */
-    int32_t kind;               /* 0 tiles, 1 row mode, 2 list (FP64 part of the mixed split) */
+    int32_t kind;               /* 0 tiles, 1 row mode (long bras, 256-lane workgroups), 2 list (FP64
+                                   part of the mixed split), 3 row mode (short bras, 64-lane) */
     int64_t nquartets;          /* quartets processed, summed over the launches (0 for kind 2) */
     double model_flops;         /* their algorithmic FLOPs (nset = 1), summed likewise */
     double ms;                  /* summed kernel time */

@@ -835,7 +835,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
         a.list = P->d_list ? P->d_list + 2 * c.list_off : nullptr;
         a.list_count = P->d_list_cnt ? P->d_list_cnt + ci : nullptr;
         a.nq = (int32_t)c.nq;
-        const int slot = (int)(2 * ci + pr) * 3;  // + kind
+        const int slot = (int)(2 * ci + pr) * 4;  // + kind
         const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
         const bool longrows = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
                               row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4) <= (size_t)ROW_LDS_MAX && !P->no_row;
@@ -861,7 +861,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
             // short bras: one 64-lane workgroup each
             a.row_pos = c.d_srowt;
             a.nrow = c.nsrow;
-            if ((rc = mark(slot + 1, c.nq - c.nq_row))) return rc;
+            if ((rc = mark(slot + 3, c.nq - c.nq_row))) return rc;
             HIPCHK(e.srow[f - 1][pr](a, s));
             a.ntiles = 0;
         } else if (longrows) {
@@ -886,7 +886,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
             // the FP32 passes above diverted large-bound quartets to the
             // list; the FP64 list pass follows
             const int f64 = c.fam[0];
-            if ((rc = mark((int)(2 * ci) * 3 + 2, 0))) return rc;
+            if ((rc = mark((int)(2 * ci) * 4 + 2, 0))) return rc;
             HIPCHK(e.list64[f64 - 1](a, s));
         }
     }
@@ -897,7 +897,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, P->events[k], P->events[k + 1]));
             jk_class_timing &t = P->timing[slots[k].first];
-            const ClassTask &c = P->cls[slots[k].first / 6];
+            const ClassTask &c = P->cls[slots[k].first / 8];
             t.ms += ms;
             t.launches += 1;
             t.nquartets += slots[k].second;
@@ -922,12 +922,12 @@ extern "C" int jk_plan_set_density_screening(jk_plan *P, double threshold) {
 extern "C" int jk_plan_profile(jk_plan *P, int32_t enable) {
     if (!P) return fail(JK_EINVAL, "plan is NULL");
     P->profile = enable != 0;
-    P->timing.assign(6 * P->cls.size(), jk_class_timing{});
+    P->timing.assign(8 * P->cls.size(), jk_class_timing{});
     for (size_t ci = 0; ci < P->cls.size(); ++ci)
         for (int k = 0; k < 2; ++k)
-            for (int kind = 0; kind < 3; ++kind) {
+            for (int kind = 0; kind < 4; ++kind) {
                 const ClassTask &c = P->cls[ci];
-                jk_class_timing &t = P->timing[(2 * ci + k) * 3 + kind];
+                jk_class_timing &t = P->timing[(2 * ci + k) * 4 + kind];
                 t.li = c.li; t.lj = c.lj; t.lk = c.lk; t.ll = c.ll;
                 t.npb = c.npb; t.npk = c.npk;
                 t.precision = (k && kind != 2) ? JK_FP32 : JK_FP64;
