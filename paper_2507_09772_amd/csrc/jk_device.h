@@ -921,6 +921,11 @@ struct K2Cfg {
     static constexpr int O_KJK = O_KIL + C::NI * C::NL;
     static constexpr int O_KJL = O_KJK + C::NJ * C::NK;
     static constexpr int DIG = O_KJL + C::NJ * C::NL;
+    // per wave: the QW digestion blocks, then every lane's partial K_JL
+    // sums of a pass ([lane][b in pass][d]), reduced over the slots without
+    // atomics
+    static constexpr int PARTW = 64 * CB * C::NL;
+    static constexpr int DIGW = QW * DIG + PARTW;
     // table index [ax][cx][bx][dx]
     static __device__ __forceinline__ constexpr int tix(int ax, int bx, int cx, int dx) {
         return ((ax * (LK + 1) + cx) * (LJ + 1) + bx) * (LL + 1) + dx;
@@ -1070,6 +1075,11 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                 wave_sync();
                 for (int t = lane; t < QW * F::DIG; t += 64) dig[t] = 0.0;
                 wave_sync();
+                double kjlp[CB][NL];
+#pragma unroll
+                for (int bb = 0; bb < CB; ++bb)
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) kjlp[bb][d] = 0.0;
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
                     if (!(valid && sv[k])) continue;
@@ -1102,7 +1112,11 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                             kik += v * djl;
                             kil[d] += v * djk;
                             kjk += v * dil[d];
-                            if (a.do_k) atomicAdd(ROW ? &rJ[b * ncols + cL + d] : &dq[F::O_KJL + b * NL + d], wq * v * dik);
+                            if constexpr (ROW) {
+                                if (a.do_k) atomicAdd(&rJ[b * ncols + cL + d], wq * v * dik);
+                            } else {
+                                kjlp[bb][d] += v * dik;
+                            }
                         }
                         if (a.do_j) atomicAdd(ROW ? &rjij[ia * NJ + b] : &dq[F::O_JIJ + ia * NJ + b], 2.0 * wq * jij);
                         if (a.do_k) atomicAdd(ROW ? &rJ[b * ncols + cK + ic] : &dq[F::O_KJK + b * NK + ic], wq * kjk);
@@ -1113,6 +1127,25 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                         if (a.do_k) atomicAdd(ROW ? &rI[ia * ncols + cL + d] : &dq[F::O_KIL + ia * NL + d], wq * kil[d]);
                     }
                     if (a.do_k) atomicAdd(ROW ? &rI[ia * ncols + cK + ic] : &dq[F::O_KIK + ia * NK + ic], wq * kik);
+                }
+                if constexpr (!ROW) {
+                    // K_JL of each quartet: sum of its lanes' partials
+                    if (a.do_k) {
+                        double *part = dig + QW * F::DIG;
+#pragma unroll
+                        for (int bb = 0; bb < CB; ++bb)
+#pragma unroll
+                            for (int d = 0; d < NL; ++d) part[lane * (CB * NL) + bb * NL + d] = wq * kjlp[bb][d];
+                        wave_sync();
+                        for (int t = lane; t < QW * CB * NL; t += 64) {
+                            const int q2 = t / (CB * NL), bd = t % (CB * NL);
+                            const int b = pass * CB + bd / NL;
+                            if (b >= NJ) continue;
+                            double sum = 0.0;
+                            for (int l2 = 0; l2 < LPQ; ++l2) sum += part[(q2 * LPQ + l2) * (CB * NL) + bd];
+                            dig[q2 * F::DIG + F::O_KJL + b * NL + bd % NL] = sum;
+                        }
+                    }
                 }
                 wave_sync();
                 if (lane_used && valid) {
@@ -1165,7 +1198,7 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
     using F = K2Cfg<LI, LJ, LK, LL>;
     constexpr int QW = F::QW, LPQ = F::LPQ;
     __shared__ R tabs[QW * F::TAB];
-    __shared__ double dig[QW * F::DIG];
+    __shared__ double dig[F::DIGW];
     const int lane = threadIdx.x;
     const int q = QW > 1 ? lane / LPQ : 0;
     const int sl = QW > 1 ? lane % LPQ : lane;
@@ -1195,13 +1228,13 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
 // ket prefix (interleaved by QW quartets), sharing the bra's K rows and J_IJ
 // in LDS; one workgroup barrier before the final flush.
 // Dynamic LDS: [nset][(NI+NJ) ncols + NI NJ] doubles, then (waves) x
-// QW x DIG doubles, then (waves) x QW x TAB reals.
+// DIGW doubles, then (waves) x QW x TAB reals.
 template <int LI, int LJ, int LK, int LL>
 struct K2RowLds {
     using F = K2Cfg<LI, LJ, LK, LL>;
     // per wave of the workgroup
     template <typename R>
-    static constexpr size_t fixed() { return (size_t)F::QW * (F::DIG * sizeof(double) + F::TAB * sizeof(R)); }
+    static constexpr size_t fixed() { return (size_t)F::DIGW * sizeof(double) + (size_t)F::QW * F::TAB * sizeof(R); }
     static constexpr size_t per_set(int ncols) {
         return sizeof(double) * ((size_t)(ncart(LI) + ncart(LJ)) * ncols + (size_t)ncart(LI) * ncart(LJ));
     }
@@ -1229,8 +1262,8 @@ __global__ void __launch_bounds__(NT) jk_k2_row(const JkArgs a_in, const BatchDe
     const int segL = a.seg_same ? 0 : a.ncolK;
     const int per_set = (NI + NJ) * ncols + NAB;
     double *rows = smem2;
-    double *dig = rows + (size_t)per_set * a.nset + (size_t)wave * QW * F::DIG;
-    R *tabs = (R *)(rows + (size_t)per_set * a.nset + NW * QW * F::DIG) + (size_t)wave * QW * F::TAB;
+    double *dig = rows + (size_t)per_set * a.nset + (size_t)wave * F::DIGW;
+    R *tabs = (R *)(rows + (size_t)per_set * a.nset + NW * F::DIGW) + (size_t)wave * QW * F::TAB;
     const int i = a.row_pos[3 * task];
     const int jbeg = a.row_pos[3 * task + 1], cnt = a.row_pos[3 * task + 2];
     const int bra = a.bra_list[i];
@@ -1298,7 +1331,7 @@ __global__ void __launch_bounds__(64) jk_k2_batch(const BatchDesc *__restrict__ 
     using F = K2Cfg<LI, LJ, LK, LL>;
     constexpr int QW = F::QW, LPQ = F::LPQ;
     __shared__ R tabs[QW * F::TAB];
-    __shared__ double dig[QW * F::DIG];
+    __shared__ double dig[F::DIGW];
     const int lane = threadIdx.x;
     const int q = QW > 1 ? lane / LPQ : 0;
     const int sl = QW > 1 ? lane % LPQ : lane;
@@ -1334,7 +1367,7 @@ __global__ void __launch_bounds__(64) jk_k2_batch_list(const BatchDesc *__restri
     using F = K2Cfg<LI, LJ, LK, LL>;
     constexpr int QW = F::QW, LPQ = F::LPQ;
     __shared__ double tabs[QW * F::TAB];
-    __shared__ double dig[QW * F::DIG];
+    __shared__ double dig[F::DIGW];
     const int lane = lane_index();
     const int q = QW > 1 ? lane / LPQ : 0;
     const bool lane_used = q < QW;
