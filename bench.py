@@ -306,6 +306,7 @@ def main():
     ap.add_argument("--dscreen", type=float, default=1e-10, help="density screening threshold")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mix-threshold", type=float, default=1e-4)
+    ap.add_argument("--top", type=int, default=12, help="kernels listed per build")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales the HBM counters)")
     args = ap.parse_args()
@@ -376,7 +377,7 @@ def main():
                 "model_flops_per_launch": dom["flops"] / dom["launches"],
                 "share_of_build": dom["ms"] / args.steps / (dt64 * 1e3)}
     whole = st.model_flops / dt64 / 1e12
-    for name, k in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])[:12]:
+    for name, k in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])[:args.top]:
         log(f"  {name:44s} {k['ms'] / args.steps:8.3f} ms/build  {k['launches'] / args.steps:4.0f} launches  "
             f"{k['flops'] / (k['ms'] * 1e-3) / 1e12 if k['ms'] > 0 else 0:6.2f} TF/s")
 

@@ -18,6 +18,7 @@
 #include "../../include/jk.h"
 #include "jk_registry.h"
 #include "tables/jk_tables.h"
+#include "tables/jk_tables_mom.h"
 #include "jk_internal.h"
 
 #include <dlfcn.h>
@@ -92,6 +93,7 @@ static int tables_for_device(Tables *out) {
         for (size_t i = 0; i < nb; ++i) bf[i] = (float)jkt_boys[i];
         if ((rc = upload((double **)&t.boys, jkt_boys, nb))) return rc;
         if ((rc = upload((float **)&t.boys32, bf.data(), nb))) return rc;
+        if ((rc = upload((double **)&t.mom, jkt_mom, (size_t)JKT_MOM_NT * JKT_MOM_COLS))) return rc;
         g_tab[dev] = t;
         g_tab_ok[dev] = true;
     }
@@ -838,9 +840,9 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
         const int slot = (int)(2 * ci + pr) * 4;  // + kind
         const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
         const bool longrows = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
-                              row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4) <= (size_t)ROW_LDS_MAX && !P->no_row;
+                              row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
         const bool shortrows = c.row_short[pr] && c.nsrow > 0 && e.srow[f - 1][pr] && (longrows || c.nrow == 0) &&
-                               row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 1) <= (size_t)ROW_LDS_MAX && !P->no_row;
+                               row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 1, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
         if (longrows || shortrows) {
             a.bra_list = c.d_bra;
             a.bra_cnt = c.d_cnt;

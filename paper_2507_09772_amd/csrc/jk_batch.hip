@@ -219,7 +219,7 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             if (c.ntiles[f - 1] <= 0) continue;
             const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
             const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
-            const size_t lds1 = row_lds_bytes(ce, f, pr, c.li, c.lj, nset, ncols, 1);
+            const size_t lds1 = row_lds_bytes(ce, f, pr, c.li, c.lj, nset, ncols, 1, c.npb);
             const int kind = c.row_ok[pr] && ce.batch_row[f - 1][pr] && lds1 <= (size_t)ROW_LDS_MAX ? 1 : 0;
             BatchDesc d{};
             JkArgs &a = d.a;

@@ -94,6 +94,7 @@ struct Tables {
     const float *hx2_32, *hw32;
     const double *boys;    // F_m on the T grid
     const float *boys32;
+    const double *mom;     // [e^-T, F_3..F_9] on the T grid (two-root rule)
 };
 
 struct JkArgs {

@@ -30,6 +30,7 @@
 
 #include "jk_common.h"
 #include "tables/jk_tables_meta.h"
+#include "tables/jk_tables_mom_meta.h"
 
 namespace jk {
 
@@ -103,6 +104,109 @@ __device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u,
     }
 }
 
+// The same rule in two stages, so that the grid row of the next primitive
+// quartet can be in flight while the current one is evaluated: rys1_fetch
+// loads the row (row 0 beyond the table end, where it is not used) and
+// rys1_eval gives exactly the values of rys1.
+template <typename R>
+struct Rys1Row {
+    static constexpr int NT = sizeof(R) == 8 ? 7 : 4;  // Taylor terms
+    R f[NT + 1];
+    R d;  // T_j - T
+};
+template <typename R>
+__device__ __forceinline__ void rys1_fetch(double T, const R *__restrict__ boys, Rys1Row<R> &row) {
+    const int j = T < JKT_BOYS_TMAX ? (int)(T * JKT_BOYS_DENSITY + 0.5) : 0;
+    row.d = (R)((double)j * (1.0 / JKT_BOYS_DENSITY) - T);
+    const R *src = boys + j * (JKT_BOYS_MMAX + 1);
+#pragma unroll
+    for (int k = 0; k <= Rys1Row<R>::NT; ++k) row.f[k] = src[k];
+}
+template <typename R>
+__device__ __forceinline__ void rys1_eval(double T, const Rys1Row<R> &row, R &u, R &w) {
+    constexpr int NT = Rys1Row<R>::NT;
+    if (T < JKT_BOYS_TMAX) {
+        const R d = row.d;
+        R f1 = row.f[NT];
+        R f0 = row.f[NT - 1];
+#pragma unroll
+        for (int k = NT - 1; k >= 1; --k) {
+            f1 = row.f[k] + f1 * d * (R)(1.0 / k);
+            f0 = row.f[k - 1] + f0 * d * (R)(1.0 / k);
+        }
+        w = f0;
+        u = f1 * rcp_<R>(f0);
+    } else {
+        const R rt = rsqrt_<R>((R)T);
+        w = (R)SQRT_PI_HALF * rt;
+        u = (R)0.5 * rt * rt;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two roots in FP64 from the moments F_0..F_3 (the defining property of the
+// rule: sum_i w_i u_i^k = F_k(T) for k = 0..3).  F_3 and e^-T are expanded
+// about the nearest grid point T_j (7 Taylor terms each, |T_j - T| <= 1/64),
+// F_2, F_1, F_0 follow by the stable downward recursion
+// F_m = (2T F_(m+1) + e^-T) / (2m+1).  The nodes are the zeros of the
+// monic orthogonal polynomial u^2 + a u + b with
+//   F_2 + a F_1 + b F_0 = 0,  F_3 + a F_2 + b F_1 = 0,
+// taken as u_+ = (-a + sqrt(a^2 - 4b)) / 2 and u_- = b / u_+ (no
+// cancellation since a < 0), with weights w_+ = (F_1 - u_- F_0) / (u_+ - u_-)
+// and w_- = F_0 - w_+.  Beyond the grid: the Gauss-Hermite limit.  One row
+// of 64 bytes per primitive quartet instead of the fit coefficients.
+// ---------------------------------------------------------------------------
+struct Rys2Row {
+    double f[JKT_MOM_COLS];  // e^-T_j, F_3(T_j) .. F_9(T_j)
+    double d;                // T_j - T
+};
+static_assert(JKT_MOM_M0 == 3 && JKT_MOM_COLS == JKT_MOM_TERMS + 1, "moment grid layout");
+
+__device__ __forceinline__ void rys2_fetch(double T, const double *__restrict__ mom, Rys2Row &row) {
+    const int j = T < JKT_MOM_TMAX ? (int)(T * JKT_MOM_DENSITY + 0.5) : 0;
+    row.d = (double)j * (1.0 / JKT_MOM_DENSITY) - T;
+    const double *src = mom + j * JKT_MOM_COLS;
+#pragma unroll
+    for (int k = 0; k < JKT_MOM_COLS; ++k) row.f[k] = src[k];
+}
+
+__device__ __forceinline__ void rys2_eval(double T, const Rys2Row &row, double (&u)[2], double (&w)[2]) {
+    if (T < JKT_MOM_TMAX) {
+        const double d = row.d;
+        double f3 = row.f[JKT_MOM_TERMS];
+        double ed = 1.0;
+#pragma unroll
+        for (int k = JKT_MOM_TERMS - 1; k >= 1; --k) {
+            f3 = row.f[k] + f3 * d * (1.0 / k);
+            ed = 1.0 + ed * d * (1.0 / k);
+        }
+        const double ex = row.f[0] * ed;
+        const double t2 = T + T;
+        const double f2 = (t2 * f3 + ex) * (1.0 / 5.0);
+        const double f1 = (t2 * f2 + ex) * (1.0 / 3.0);
+        const double f0 = t2 * f1 + ex;
+        const double rdet = rcp64(f1 * f1 - f0 * f2);
+        const double a = (f0 * f3 - f1 * f2) * rdet;
+        const double b = (f2 * f2 - f1 * f3) * rdet;
+        const double disc = a * a - 4.0 * b;
+        const double up = 0.5 * (disc * rsq64(disc) - a);
+        const double um = b * rcp64(up);
+        const double wp = (f1 - um * f0) * rcp64(up - um);
+        u[0] = um;
+        u[1] = up;
+        w[0] = f0 - wp;
+        w[1] = wp;
+    } else {
+        const double rt = rsq64(T);
+        const double rT = rt * rt;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            u[i] = jkt_mom_hx2[i] * rT;
+            w[i] = jkt_mom_hw[i] * rt;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // N >= 2 roots: piecewise polynomial fits on unit intervals of T (Horner on
 // all 2N functions at once, degree-major layout), large-T Gauss-Hermite limit.
@@ -111,6 +215,14 @@ template <int N, typename R>
 __device__ __forceinline__ void rys_roots(double T, const Tables &tab, R (&u)[N], R (&w)[N]) {
     if constexpr (N == 1) {
         rys1<R>(T, TabSel<R>::boys(tab), u[0], w[0]);
+    } else if constexpr (N == 2) {
+        // FP64 for both precisions (single-precision kernels round it)
+        Rys2Row row;
+        rys2_fetch(T, tab.mom, row);
+        double ud[2], wd[2];
+        rys2_eval(T, row, ud, wd);
+        u[0] = (R)ud[0]; u[1] = (R)ud[1];
+        w[0] = (R)wd[0]; w[1] = (R)wd[1];
     } else {
         static_assert(jkt_rys_h[N] == 1.0, "unit intervals assumed");
         constexpr int NF = 2 * N;
@@ -145,6 +257,36 @@ __device__ __forceinline__ void rys_roots(double T, const Tables &tab, R (&u)[N]
         }
     }
 }
+
+// Root rules evaluated in two stages (the table row of one primitive
+// quartet is loaded while the previous one is evaluated): one and two roots.
+template <int N, typename R>
+struct RootPipe {
+    static constexpr bool ok = false;
+};
+template <typename R>
+struct RootPipe<1, R> {
+    static constexpr bool ok = true;
+    using Row = Rys1Row<R>;
+    static __device__ __forceinline__ void fetch(double T, const Tables &tab, Row &row) {
+        rys1_fetch<R>(T, TabSel<R>::boys(tab), row);
+    }
+    static __device__ __forceinline__ void eval(double T, const Row &row, const Tables &, R (&u)[1], R (&w)[1]) {
+        rys1_eval<R>(T, row, u[0], w[0]);
+    }
+};
+template <typename R>
+struct RootPipe<2, R> {
+    static constexpr bool ok = true;
+    using Row = Rys2Row;
+    static __device__ __forceinline__ void fetch(double T, const Tables &tab, Row &row) { rys2_fetch(T, tab.mom, row); }
+    static __device__ __forceinline__ void eval(double T, const Row &row, const Tables &, R (&u)[2], R (&w)[2]) {
+        double ud[2], wd[2];
+        rys2_eval(T, row, ud, wd);
+        u[0] = (R)ud[0]; u[1] = (R)ud[1];
+        w[0] = (R)wd[0]; w[1] = (R)wd[1];
+    }
+};
 
 // single root r of an N-root rule (the 2-D table builders of family 2)
 template <int N, typename R>
@@ -392,9 +534,17 @@ struct PQuart {
     R PQ[3], PA[3], QC[3];
 };
 
+// First stage of a primitive quartet's geometry: 1/sqrt(p+q), rho and T
+// (what the root table lookup needs); prim_rest finishes the quartet.
 template <typename R>
-__device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const PrimPair &pk) {
-    PQuart<R> g;
+struct PT {
+    double T, rho;
+    R rs;  // 1 / sqrt(p + q)
+};
+
+template <typename R>
+__device__ __forceinline__ PT<R> prim_T(const PrimPair &pb, const PrimPair &pk) {
+    PT<R> t;
     if constexpr (sizeof(R) == 4) {
         // single precision quartets: only the centre differences and the
         // prefactor's product of pair factors are formed in FP64
@@ -405,46 +555,54 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
 #pragma unroll
         for (int x = 0; x < 3; ++x) {
             const float d = (float)(pb.P[x] - pk.P[x]);
-            g.PQ[x] = d;
             pq2 += d * d;
-            g.PA[x] = (float)pb.PA[x];
-            g.QC[x] = (float)pk.PA[x];
         }
         const float rho = p * q * rpq;
-        g.rho = (double)rho;
-        g.T = (double)(rho * pq2);
-        g.rpq = rpq;
-        g.fq = q * rpq;
-        g.fp = p * rpq;
-        g.pref = (float)(TWO_PI_2_5 * pb.kp * pk.kp) * rs;
-        g.hb = (float)pb.h;
-        g.hk = (float)pk.h;
-        return g;
-    }
-    const double p = pb.p, q = pk.p;
-    const double rs = rsq64(p + q);
-    const double rpq = rs * rs;
-    double pq2 = 0.0, d[3];
+        t.rho = (double)rho;
+        t.T = (double)(rho * pq2);
+        t.rs = rs;
+    } else {
+        const double p = pb.p, q = pk.p;
+        const double rs = rsq64(p + q);
+        const double rpq = rs * rs;
+        double pq2 = 0.0;
 #pragma unroll
-    for (int x = 0; x < 3; ++x) {
-        d[x] = pb.P[x] - pk.P[x];
-        pq2 += d[x] * d[x];
+        for (int x = 0; x < 3; ++x) {
+            const double d = pb.P[x] - pk.P[x];
+            pq2 += d * d;
+        }
+        t.rho = p * q * rpq;
+        t.T = t.rho * pq2;
+        t.rs = rs;
     }
-    g.rho = p * q * rpq;
-    g.T = g.rho * pq2;
-    g.rpq = (R)rpq;
-    g.fq = (R)(q * rpq);
-    g.fp = (R)(p * rpq);
-    g.pref = (R)(TWO_PI_2_5 * pb.kp * pk.kp * rs);
+    return t;
+}
+
+template <typename R>
+__device__ __forceinline__ PQuart<R> prim_rest(const PrimPair &pb, const PrimPair &pk, const PT<R> &t) {
+    PQuart<R> g;
+    g.T = t.T;
+    g.rho = t.rho;
+    const R rs = t.rs, rpq = rs * rs;
+    g.rpq = rpq;
+    g.fq = (R)pk.p * rpq;
+    g.fp = (R)pb.p * rpq;
+    if constexpr (sizeof(R) == 4) g.pref = (float)(TWO_PI_2_5 * pb.kp * pk.kp) * rs;
+    else g.pref = TWO_PI_2_5 * pb.kp * pk.kp * rs;
     g.hb = (R)pb.h;
     g.hk = (R)pk.h;
 #pragma unroll
     for (int x = 0; x < 3; ++x) {
-        g.PQ[x] = (R)d[x];
+        g.PQ[x] = (R)(pb.P[x] - pk.P[x]);
         g.PA[x] = (R)pb.PA[x];
         g.QC[x] = (R)pk.PA[x];
     }
     return g;
+}
+
+template <typename R>
+__device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const PrimPair &pk) {
+    return prim_rest<R>(pb, pk, prim_T<R>(pb, pk));
 }
 
 // ===========================================================================
@@ -452,59 +610,102 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
 // registers; digestion reduces J_IJ across the wave when the bra is uniform
 // (tiles) and sends the other blocks straight to FP64 atomics.
 // ===========================================================================
-// Contracted Cartesian block of one quartet into V (registers).
+// Adds the N_r roots of one primitive quartet to the contracted block V.
 template <int LI, int LJ, int LK, int LL, typename R>
-__device__ __forceinline__ void k1_compute(const JkArgs &a, const PairRec &B, const PairRec &Kt, int npb, int npk,
-                                           R (&V)[ncart4(LI, LJ, LK, LL)]) {
+__device__ __forceinline__ void k1_roots_acc(const PQuart<R> &g, const R *u, const R *w, const R (&ab)[3],
+                                             const R (&cd)[3], R (&V)[ncart4(LI, LJ, LK, LL)]) {
     using C = Cls<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const R t = u[r];
+        const R b00 = (R)0.5 * t * g.rpq;
+        const R b10 = g.hb * ((R)1 - g.fq * t);
+        const R b01 = g.hk * ((R)1 - g.fp * t);
+        R I[3][C::S];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            const R c00 = g.PA[x] - g.fq * t * g.PQ[x];
+            const R c00p = g.QC[x] + g.fp * t * g.PQ[x];
+            const R s = x == 2 ? w[r] * g.pref : (R)1;
+            R *dst = I[x];
+            rys2d<LI, LJ, LK, LL, R>(c00, c00p, b00, b10, b01, ab[x], cd[x], s,
+                                     [&](int ia, int ib2, int ic, int id, R v) { dst[C::t4(ia, ib2, ic, id)] = v; });
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int k = 0; k < NK; ++k)
+#pragma unroll
+                    for (int l = 0; l < NL; ++l) {
+                        const int ix = C::t4(cart_comp(LI, i, 0), cart_comp(LJ, j, 0), cart_comp(LK, k, 0), cart_comp(LL, l, 0));
+                        const int iy = C::t4(cart_comp(LI, i, 1), cart_comp(LJ, j, 1), cart_comp(LK, k, 1), cart_comp(LL, l, 1));
+                        const int iz = C::t4(cart_comp(LI, i, 2), cart_comp(LJ, j, 2), cart_comp(LK, k, 2), cart_comp(LL, l, 2));
+                        V[((i * NJ + j) * NK + k) * NL + l] += I[0][ix] * I[1][iy] * I[2][iz];
+                    }
+    }
+}
+
+// Contracted Cartesian block of one quartet into V (registers); pbat(ib)
+// returns the bra's primitive pair record ib.  RS: the range-separated
+// operators (omega != 0) are compiled in; the Coulomb instance has no
+// trace of them (given the chance, the compiler evaluates the root scaling
+// of the other variant on every primitive quartet).
+template <int LI, int LJ, int LK, int LL, typename R, bool RS, typename PBF>
+__device__ __forceinline__ void k1_compute_op(const JkArgs &a, const PairRec &B, const PairRec &Kt, PBF &&pbat, int npb,
+                                              int npk, R (&V)[ncart4(LI, LJ, LK, LL)]) {
+    using C = Cls<LI, LJ, LK, LL>;
+    constexpr int NR = C::NR;
 #pragma unroll
     for (int e = 0; e < C::NC; ++e) V[e] = (R)0;
     const R ab[3] = {(R)B.ab[0], (R)B.ab[1], (R)B.ab[2]};
     const R cd[3] = {(R)Kt.ab[0], (R)Kt.ab[1], (R)Kt.ab[2]};
     // ket primitive outer (one vector load each), bra primitive inner (the
-    // bra is uniform across a tile, so its records come through scalar loads)
+    // bra is uniform across a tile or row task)
+    if constexpr (!RS && RootPipe<NR, R>::ok) {
+        // the root table row of the next primitive quartet is loaded while
+        // the current one's recurrences run
+        using P = RootPipe<NR, R>;
+        for (int ik = 0; ik < npk; ++ik) {
+            const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
+            PT<R> t = prim_T<R>(pbat(0), pk);
+            typename P::Row row;
+            P::fetch(t.T, a.tab, row);
+            for (int ib = 0; ib < npb; ++ib) {
+                const PQuart<R> g = prim_rest<R>(pbat(ib), pk, t);
+                R u[NR], w[NR];
+                P::eval(g.T, row, a.tab, u, w);
+                if (ib + 1 < npb) {
+                    t = prim_T<R>(pbat(ib + 1), pk);
+                    P::fetch(t.T, a.tab, row);
+                }
+                k1_roots_acc<LI, LJ, LK, LL, R>(g, u, w, ab, cd, V);
+            }
+        }
+        return;
+    }
+    const int vb = RS ? variant_begin(a.omega) : 0, ve = RS ? variant_end(a.omega) : 1;
     for (int ik = 0; ik < npk; ++ik) {
         const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
         for (int ib = 0; ib < npb; ++ib) {
-            const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
-            const PQuart<R> g = prim_quartet<R>(pb, pk);
-            for (int var = variant_begin(a.omega); var < variant_end(a.omega); ++var) {
-            R u[NR], w[NR];
-            rys_roots_op<NR, R>(g.T, g.rho, a.omega, var, a.tab, u, w);
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const R t = u[r];
-                const R b00 = (R)0.5 * t * g.rpq;
-                const R b10 = g.hb * ((R)1 - g.fq * t);
-                const R b01 = g.hk * ((R)1 - g.fp * t);
-                R I[3][C::S];
-#pragma unroll
-                for (int x = 0; x < 3; ++x) {
-                    const R c00 = g.PA[x] - g.fq * t * g.PQ[x];
-                    const R c00p = g.QC[x] + g.fp * t * g.PQ[x];
-                    const R s = x == 2 ? w[r] * g.pref : (R)1;
-                    R *dst = I[x];
-                    rys2d<LI, LJ, LK, LL, R>(c00, c00p, b00, b10, b01, ab[x], cd[x], s,
-                                             [&](int ia, int ib2, int ic, int id, R v) { dst[C::t4(ia, ib2, ic, id)] = v; });
-                }
-#pragma unroll
-                for (int i = 0; i < NI; ++i)
-#pragma unroll
-                    for (int j = 0; j < NJ; ++j)
-#pragma unroll
-                        for (int k = 0; k < NK; ++k)
-#pragma unroll
-                            for (int l = 0; l < NL; ++l) {
-                                const int ix = C::t4(cart_comp(LI, i, 0), cart_comp(LJ, j, 0), cart_comp(LK, k, 0), cart_comp(LL, l, 0));
-                                const int iy = C::t4(cart_comp(LI, i, 1), cart_comp(LJ, j, 1), cart_comp(LK, k, 1), cart_comp(LL, l, 1));
-                                const int iz = C::t4(cart_comp(LI, i, 2), cart_comp(LJ, j, 2), cart_comp(LK, k, 2), cart_comp(LL, l, 2));
-                                V[((i * NJ + j) * NK + k) * NL + l] += I[0][ix] * I[1][iy] * I[2][iz];
-                            }
-            }
+            const PQuart<R> g = prim_quartet<R>(pbat(ib), pk);
+            for (int var = vb; var < ve; ++var) {
+                R u[NR], w[NR];
+                if constexpr (RS) rys_roots_op<NR, R>(g.T, g.rho, a.omega, var, a.tab, u, w);
+                else rys_roots<NR, R>(g.T, a.tab, u, w);
+                k1_roots_acc<LI, LJ, LK, LL, R>(g, u, w, ab, cd, V);
             }
         }
     }
+}
+
+template <int LI, int LJ, int LK, int LL, typename R, typename PBF>
+__device__ __forceinline__ void k1_compute(const JkArgs &a, const PairRec &B, const PairRec &Kt, PBF &&pbat, int npb,
+                                           int npk, R (&V)[ncart4(LI, LJ, LK, LL)]) {
+    if (a.omega == 0.0) k1_compute_op<LI, LJ, LK, LL, R, false>(a, B, Kt, pbat, npb, npk, V);
+    else k1_compute_op<LI, LJ, LK, LL, R, true>(a, B, Kt, pbat, npb, npk, V);
 }
 
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
@@ -516,7 +717,8 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
     const PairRec B = a.pairs[bra];
     const PairRec Kt = a.pairs[ket];
     R V[C::NC];
-    k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, BRA_UNIFORM ? a.npb : B.npp, MODE == MODE_JK ? a.npk : Kt.npp, V);
+    k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, [&](int ib) { return a.pp[B.pp_off + ib * B.pp_stride]; },
+                                  BRA_UNIFORM ? a.npb : B.npp, MODE == MODE_JK ? a.npk : Kt.npp, V);
     if constexpr (MODE == MODE_EXPORT) {
         if (valid) {
             double *o = a.out + gout * (NAB * NCD);
@@ -714,8 +916,9 @@ __device__ __forceinline__ int batch_desc(const BatchDesc *__restrict__ d, int n
 // (a row task: list position, first and end ket).  K'_IK, K'_IL (row block
 // of shell I) and K'_JK, K'_JL (row block of J) accumulate in LDS over the
 // compressed ket-type columns, J'_IJ in LDS, and only J'_KL goes to global
-// atomics per quartet.  Dynamic LDS layout, per density: [NI rows | NJ rows]
-// x ncols, then NAB for J'_IJ.  NT = 256 for long bras, 64 for short ones;
+// atomics per quartet.  Dynamic LDS layout: the bra's npb primitive pair
+// records, then per density [NI rows | NJ rows] x ncols and NAB for J'_IJ.
+// NT = 256 for long bras, 64 for short ones;
 // BATCH: the task indexes the row tasks of many descriptors (molecules).
 template <int LI, int LJ, int LK, int LL, typename R, int NT>
 __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
@@ -729,9 +932,13 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
     const int segL = a.seg_same ? 0 : a.ncolK;
     const int per_set = (NI + NJ) * ncols + NAB;
-    for (int t = tid; t < per_set * a.nset; t += NT) rowmem[t] = 0.0;
-    __syncthreads();
     const PairRec B = a.pairs[bra];
+    // the bra's primitive pair records, then the rows
+    PrimPair *sbra = reinterpret_cast<PrimPair *>(rowmem);
+    double *rows = rowmem + (size_t)a.npb * (sizeof(PrimPair) / sizeof(double));
+    for (int t = tid; t < a.npb; t += NT) sbra[t] = a.pp[B.pp_off + t * B.pp_stride];
+    for (int t = tid; t < per_set * a.nset; t += NT) rows[t] = 0.0;
+    __syncthreads();
     const int n = a.nao;
     for (int j0 = jbeg; j0 < cnt; j0 += NT) {
         const int j = j0 + tid;
@@ -743,11 +950,11 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
         screen_quartet(a, B, Kt, valid, hi);
         if (a.sel == SEL_LOW) list_append(a, hi, bra, ket);
         R V[C::NC];
-        k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, a.npb, a.npk, V);
+        k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, [&](int ib) { return sbra[ib]; }, a.npb, a.npk, V);
         const int cK = a.tpos[Kt.ish] * NK, cL = segL + a.tpos[Kt.jsh] * NL;
         for (int s = 0; s < a.nset; ++s) {
             const double *D = a.D + s * a.mstride;
-            double *rm = rowmem + s * per_set;
+            double *rm = rows + s * per_set;
             double *rI = rm, *rJ = rm + NI * ncols, *jij = rm + (NI + NJ) * ncols;
             if (a.do_j) {
                 double dij[NAB], dkl[NCD];
@@ -856,7 +1063,7 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
     __syncthreads();
     // flush nonzero entries to the global J', K'
     for (int s = 0; s < a.nset; ++s) {
-        const double *rm = rowmem + s * per_set;
+        const double *rm = rows + s * per_set;
         double *Jm = a.J + s * a.mstride;
         double *Km = a.K + s * a.mstride;
         for (int t = tid; t < per_set; t += NT) {

@@ -26,10 +26,12 @@ struct ClassEntry {
     BatchRowLauncher batch_row[2][2];  // 64-lane row tasks of many descriptors
 };
 
-// LDS bytes of one row-mode workgroup of nw waves: the fixed part plus nset
+// LDS bytes of one row-mode workgroup of nw waves: the fixed part (per wave;
+// family 1 instead keeps the bra's npb primitive pair records) plus nset
 // copies of the bra's K rows over ncols compressed columns and its J_IJ block.
-inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj, int nset, int ncols, int nw) {
-    return (size_t)nw * e.row_fixed[fam - 1][pr] +
+inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj, int nset, int ncols, int nw,
+                            int npb) {
+    return (size_t)nw * e.row_fixed[fam - 1][pr] + (fam == 1 ? sizeof(PrimPair) * (size_t)npb : 0) +
            sizeof(double) * (size_t)nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj));
 }
 

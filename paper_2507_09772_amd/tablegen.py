@@ -21,6 +21,11 @@ Tables (all derived here from their mathematical definitions):
   moment to 1e-16 relative.
 * Boys function grid: F_m(T_j) on T_j = j / BOYS_DENSITY for the Taylor
   expansion F_m(T_j + d) = sum_k F_(m+k)(T_j) (-d)^k / k!.
+* Moment grid for the two-root rule: e^(-T_j) and F_3..F_9 at the same
+  T_j, up to the point where the Gauss-Hermite limit of n = 2 takes over.
+  The kernels expand F_3 and e^(-T) about the nearest T_j, recover
+  F_2, F_1, F_0 by downward recursion and solve the two-point Gauss rule of
+  the moments F_0..F_3 in closed form.
 * Real solid harmonic coefficients (spherical <-> Cartesian), obtained by a
   least-squares projection of scipy's spherical harmonics onto monomials and
   normalised with the monomial overlap in units of the x^l norm.
@@ -41,6 +46,10 @@ BOYS_TMAX = 40.0    # beyond: F_0 = sqrt(pi/T)/2 and upward recursion
 BOYS_MMAX = 8       # highest tabulated order (F_1 with 7 Taylor terms)
 DPS = 50
 LMAX = 4
+
+MOM_M0 = 3          # first tabulated order of the moment grid
+MOM_TERMS = 7       # Taylor terms of F_3 and of exp
+MOM_TMAX = 46.0     # = the n = 2 Gauss-Hermite switch point (tmax_for(2))
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "tables", "jk_tables.h")
 
@@ -213,6 +222,39 @@ def boys_table():
     return tab
 
 
+def moment_table():
+    """Rows [e^(-T_j), F_3(T_j), ..., F_9(T_j)], T_j = j / BOYS_DENSITY."""
+    mp = _mp()
+    nt = int(MOM_TMAX * BOYS_DENSITY) + 1
+    tab = np.zeros((nt, 1 + MOM_TERMS))
+    for j in range(nt):
+        T = mp_frac(j, BOYS_DENSITY)
+        F = boys_mp(MOM_M0 + MOM_TERMS - 1, T)
+        tab[j] = [float(mp.exp(-T))] + [float(f) for f in F[MOM_M0:]]
+    return tab
+
+
+def write_moment_header(mom, path=None):
+    """jk_tables_mom_meta.h (sizes, for device code) and jk_tables_mom.h
+    (the grid, for the host copy)."""
+    d = os.path.dirname(path or OUT)
+    meta = ["/* Generated by paper_2507_09772_amd/tablegen.py -- do not edit. */", "#pragma once", "",
+            f"#define JKT_MOM_M0 {MOM_M0}", f"#define JKT_MOM_TERMS {MOM_TERMS}",
+            f"#define JKT_MOM_COLS {mom.shape[1]}", f"#define JKT_MOM_NT {mom.shape[0]}",
+            f"#define JKT_MOM_DENSITY {BOYS_DENSITY}", f"#define JKT_MOM_TMAX {MOM_TMAX!r}", ""]
+    # the n = 2 large-T limit as constants (no table load on that branch)
+    xs, ws = hermite_half(2)
+    meta.append("static constexpr double jkt_mom_hx2[2] = {" + ", ".join(repr(float(x) ** 2) for x in xs) + "};")
+    meta.append("static constexpr double jkt_mom_hw[2] = {" + ", ".join(repr(float(w)) for w in ws) + "};")
+    data = ["/* Generated by paper_2507_09772_amd/tablegen.py -- do not edit. */", "#pragma once",
+            '#include "jk_tables_mom_meta.h"', "",
+            "static const double jkt_mom[JKT_MOM_NT * JKT_MOM_COLS] = {", _fmt(mom.ravel()), "};"]
+    with open(os.path.join(d, "jk_tables_mom_meta.h"), "w") as f:
+        f.write("\n".join(meta) + "\n")
+    with open(os.path.join(d, "jk_tables_mom.h"), "w") as f:
+        f.write("\n".join(data) + "\n")
+
+
 def mp_frac(a, b):
     mp = _mp()
     return mp.mpf(a) / b
@@ -330,6 +372,12 @@ def write_header(rys, boys, c2s, path=OUT):
 
 
 def main():
+    if "--moments" in sys.argv[1:]:
+        # the moment grid alone (seconds)
+        write_moment_header(moment_table())
+        print("wrote moment grid", file=sys.stderr)
+        return
+    write_moment_header(moment_table())
     nmax = int(sys.argv[1]) if len(sys.argv) > 1 else NMAX
     rys = rys_tables(nmax=nmax)
     boys = boys_table()
