@@ -106,8 +106,8 @@ __device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u,
 
 // The same rule in two stages, so that the grid row of the next primitive
 // quartet can be in flight while the current one is evaluated: rys1_fetch
-// loads the row (row 0 beyond the table end, where it is not used) and
-// rys1_eval gives exactly the values of rys1.
+// loads the row (lanes beyond the table end load nothing) and rys1_eval
+// gives exactly the values of rys1.
 template <typename R>
 struct Rys1Row {
     static constexpr int NT = sizeof(R) == 8 ? 7 : 4;  // Taylor terms
@@ -116,11 +116,17 @@ struct Rys1Row {
 };
 template <typename R>
 __device__ __forceinline__ void rys1_fetch(double T, const R *__restrict__ boys, Rys1Row<R> &row) {
-    const int j = T < JKT_BOYS_TMAX ? (int)(T * JKT_BOYS_DENSITY + 0.5) : 0;
-    row.d = (R)((double)j * (1.0 / JKT_BOYS_DENSITY) - T);
-    const R *src = boys + j * (JKT_BOYS_MMAX + 1);
+    if (T < JKT_BOYS_TMAX) {
+        const int j = (int)(T * JKT_BOYS_DENSITY + 0.5);
+        row.d = (R)((double)j * (1.0 / JKT_BOYS_DENSITY) - T);
+        const R *src = boys + j * (JKT_BOYS_MMAX + 1);
 #pragma unroll
-    for (int k = 0; k <= Rys1Row<R>::NT; ++k) row.f[k] = src[k];
+        for (int k = 0; k <= Rys1Row<R>::NT; ++k) row.f[k] = src[k];
+    } else {
+        row.d = (R)0;
+#pragma unroll
+        for (int k = 0; k <= Rys1Row<R>::NT; ++k) row.f[k] = (R)0;
+    }
 }
 template <typename R>
 __device__ __forceinline__ void rys1_eval(double T, const Rys1Row<R> &row, R &u, R &w) {
@@ -163,11 +169,17 @@ struct Rys2Row {
 static_assert(JKT_MOM_M0 == 3 && JKT_MOM_COLS == JKT_MOM_TERMS + 1, "moment grid layout");
 
 __device__ __forceinline__ void rys2_fetch(double T, const double *__restrict__ mom, Rys2Row &row) {
-    const int j = T < JKT_MOM_TMAX ? (int)(T * JKT_MOM_DENSITY + 0.5) : 0;
-    row.d = (double)j * (1.0 / JKT_MOM_DENSITY) - T;
-    const double *src = mom + j * JKT_MOM_COLS;
+    if (T < JKT_MOM_TMAX) {
+        const int j = (int)(T * JKT_MOM_DENSITY + 0.5);
+        row.d = (double)j * (1.0 / JKT_MOM_DENSITY) - T;
+        const double *src = mom + j * JKT_MOM_COLS;
 #pragma unroll
-    for (int k = 0; k < JKT_MOM_COLS; ++k) row.f[k] = src[k];
+        for (int k = 0; k < JKT_MOM_COLS; ++k) row.f[k] = src[k];
+    } else {
+        row.d = 0.0;
+#pragma unroll
+        for (int k = 0; k < JKT_MOM_COLS; ++k) row.f[k] = 0.0;
+    }
 }
 
 __device__ __forceinline__ void rys2_eval(double T, const Rys2Row &row, double (&u)[2], double (&w)[2]) {
@@ -610,6 +622,21 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
 // registers; digestion reduces J_IJ across the wave when the bra is uniform
 // (tiles) and sends the other blocks straight to FP64 atomics.
 // ===========================================================================
+// Waits for the loads of a record here, once: values that are still
+// loading at the top of a loop make the compiler wait for every load issued
+// since (here: the next quartet's root table row) wherever they are used.
+__device__ __forceinline__ void settle(double &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void settle(PrimPair &r) {
+    settle(r.p);
+    settle(r.h);
+    settle(r.kp);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        settle(r.P[x]);
+        settle(r.PA[x]);
+    }
+}
+
 // Adds the N_r roots of one primitive quartet to the contracted block V.
 template <int LI, int LJ, int LK, int LL, typename R>
 __device__ __forceinline__ void k1_roots_acc(const PQuart<R> &g, const R *u, const R *w, const R (&ab)[3],
@@ -669,7 +696,8 @@ __device__ __forceinline__ void k1_compute_op(const JkArgs &a, const PairRec &B,
         // the current one's recurrences run
         using P = RootPipe<NR, R>;
         for (int ik = 0; ik < npk; ++ik) {
-            const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
+            PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
+            settle(pk);
             PT<R> t = prim_T<R>(pbat(0), pk);
             typename P::Row row;
             P::fetch(t.T, a.tab, row);
