@@ -626,6 +626,15 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
 // loading at the top of a loop make the compiler wait for every load issued
 // since (here: the next quartet's root table row) wherever they are used.
 __device__ __forceinline__ void settle(double &x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void settle(float &x) { asm volatile("" : "+v"(x)); }
+// one of three values by index, as selects on opaque registers
+template <typename R>
+__device__ __forceinline__ R sel3(int x, R v0, R v1, R v2) {
+    settle(v0);
+    settle(v1);
+    settle(v2);
+    return x == 0 ? v0 : (x == 1 ? v1 : v2);
+}
 __device__ __forceinline__ void settle(PrimPair &r) {
     settle(r.p);
     settle(r.h);
@@ -1127,10 +1136,11 @@ __global__ void __launch_bounds__(NT) jk_k1_row(const JkArgs a, const BatchDesc 
 // ===========================================================================
 // Family 2: a lane group per quartet.  Lane slot (a, c) owns the elements
 // (a b | c d) for all b in the current pass's chunk and all d.  Per
-// primitive quartet, lanes build the 2-D tables I_x, I_y, I_z of every root
+// primitive quartet, lanes first evaluate the roots and weights (one lane
+// per root) into LDS, then build the 2-D tables I_x, I_y, I_z of every root
 // into LDS (one task = one root and direction), then every slot accumulates
 // its elements from LDS.  Digestion: per slot partial sums, reduced across
-// the group with LDS atomics, then one FP64 global atomic per block element.
+// the group in LDS, then one FP64 global atomic per block element.
 // ===========================================================================
 template <int LI, int LJ, int LK, int LL>
 struct K2Cfg {
@@ -1253,9 +1263,13 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                     const R b00 = (R)0.5 * u * g.rpq;
                     const R b10 = g.hb * ((R)1 - g.fq * u);
                     const R b01 = g.hk * ((R)1 - g.fp * u);
-                    R pqx = g.PQ[0], pax = g.PA[0], qcx = g.QC[0], abx = ab[0], cdx = cd[0];
-                    if (x == 1) { pqx = g.PQ[1]; pax = g.PA[1]; qcx = g.QC[1]; abx = ab[1]; cdx = cd[1]; }
-                    if (x == 2) { pqx = g.PQ[2]; pax = g.PA[2]; qcx = g.QC[2]; abx = ab[2]; cdx = cd[2]; }
+                    // the direction's operands by value selects (an indexed
+                    // read makes the compiler keep a scratch copy of them)
+                    const R pqx = sel3(x, g.PQ[0], g.PQ[1], g.PQ[2]);
+                    const R pax = sel3(x, g.PA[0], g.PA[1], g.PA[2]);
+                    const R qcx = sel3(x, g.QC[0], g.QC[1], g.QC[2]);
+                    const R abx = sel3(x, ab[0], ab[1], ab[2]);
+                    const R cdx = sel3(x, cd[0], cd[1], cd[2]);
                     const R c00 = pax - g.fq * u * pqx;
                     const R c00p = qcx + g.fp * u * pqx;
                     const R sc2 = x == 2 ? (has ? w * g.pref : (R)0) : (R)1;
