@@ -146,6 +146,12 @@ __global__ void k_fill_i32(int32_t *p, int n) {
     for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
 }
 
+__global__ void k_jp_scatter(const PairRec *pairs, const int32_t *lsh, const double *jp, int64_t jpstride, double *Jc,
+                             int64_t mstride, int naoc, int npair, int64_t nt) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+        jp_scatter_elem(pairs, lsh, jp, jpstride, Jc, mstride, naoc, npair, t);
+}
+
 __global__ void k_fill(double *p, int64_t n, double v) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) p[t] = v;
 }
@@ -335,12 +341,23 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
     if (npp_tot > INT32_MAX) return fail(JK_EUNSUPPORTED, "too many primitive pairs");
     const int npair = (int)P->hpairs.size();
     const int npt0 = (int)ptype_first.size();
+    // the pair-ordered J' buffer has the same type-major layout
+    std::vector<int64_t> ptype_jpbase(npt0);
+    int64_t jp_tot = 0;
+    for (int pt = 0; pt < npt0; ++pt) {
+        const PairRec &r0 = P->hpairs[ptype_first[pt]];
+        ptype_jpbase[pt] = jp_tot;
+        jp_tot += (int64_t)ptype_count[pt] * ncart(P->l[r0.ish]) * ncart(P->l[r0.jsh]);
+    }
+    if (jp_tot > INT32_MAX) return fail(JK_EUNSUPPORTED, "too many shell-pair elements");
+    P->njp = jp_tot;
     auto place_pairs = [&]() {
         for (int pt = 0; pt < npt0; ++pt)
             for (int k = 0; k < ptype_count[pt]; ++k) {
                 PairRec &r = P->hpairs[ptype_first[pt] + k];
                 r.pp_off = ptype_ppbase[pt] + k;
                 r.pp_stride = ptype_count[pt];
+                r.jp_off = (int32_t)(ptype_jpbase[pt] + k);
             }
         P->pair_of.assign((size_t)ns * ns, -1);
         for (int p = 0; p < npair; ++p) {
@@ -730,10 +747,13 @@ static int ensure_scratch(jk_plan *P, int nset, bool need_dc) {
     if (P->scratch_nset < nset) {
         if (P->d_Jc) { (void)hipFree(P->d_Jc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Jc)); }
         if (P->d_Kc) { (void)hipFree(P->d_Kc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Kc)); }
-        P->d_Jc = P->d_Kc = nullptr;
+        if (P->d_jp) { (void)hipFree(P->d_jp); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_jp)); }
+        P->d_Jc = P->d_Kc = P->d_jp = nullptr;
         P->scratch_nset = 0;
         int rc;
-        if ((rc = P->alloc(&P->d_Jc, m * nset)) || (rc = P->alloc(&P->d_Kc, m * nset))) return rc;
+        if ((rc = P->alloc(&P->d_Jc, m * nset)) || (rc = P->alloc(&P->d_Kc, m * nset)) ||
+            (rc = P->alloc(&P->d_jp, (size_t)P->njp * nset)))
+            return rc;
         P->scratch_nset = nset;
     }
     if (need_dc && P->dc_nset < nset) {
@@ -776,6 +796,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     }
     hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Jc, (int64_t)(nset * m), 0.0);
     hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Kc, (int64_t)(nset * m), 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * P->njp, 256)), dim3(256), 0, s, P->d_jp, (int64_t)nset * P->njp, 0.0);
     HIPCHK(hipGetLastError());
     if (precision == JK_MIXED || P->dscreen > 0.0) {
         hipLaunchKernelGGL(k_dmax, dim3((P->ns * P->ns + 255) / 256), dim3(256), 0, s, Dc, P->maps.aoc, P->maps.l, P->ns, P->naoc, nset, P->d_dmax);
@@ -788,6 +809,8 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     a.J = P->d_Jc;
     a.K = P->d_Kc;
     a.mstride = (int64_t)m;
+    a.jp = P->d_jp;
+    a.jpstride = P->njp;
     a.nao = P->naoc;
     a.nset = nset;
     a.do_j = do_j;
@@ -908,6 +931,12 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     }
     const int acc = (flags & JK_ACCUMULATE) ? 1 : 0;
     const int64_t mo = (int64_t)nset * P->nao * P->nao;
+    const int npair = (int)P->hpairs.size();
+    if (do_j) {
+        const int64_t nt = (int64_t)nset * npair * 64;
+        hipLaunchKernelGGL(k_jp_scatter, dim3(grid_for(nt, 256)), dim3(256), 0, s, P->d_pairs, P->maps.l, P->d_jp, P->njp,
+                           P->d_Jc, (int64_t)m, P->naoc, npair, nt);
+    }
     if (do_j) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Jc, J, P->nao, P->naoc, nset, P->sph, acc);
     if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Kc, K, P->nao, P->naoc, nset, P->sph, acc);
     HIPCHK(hipGetLastError());

@@ -29,8 +29,11 @@ struct MolDesc {
     const double *D;         // caller's density [nset][nao][nao]
     double *J, *K;           // caller's outputs
     double *Dc, *Jc, *Kc;    // batch scratch [nset][naoc][naoc]
+    double *jp;              // pair-ordered J'_KL [nset][njp]
+    const PairRec *pairs;
+    int64_t njp;
     float *dmax;             // [ns][ns]
-    int32_t nao, naoc, ns, sph;
+    int32_t nao, naoc, ns, sph, npair;
 };
 
 // Dc = Cartesian density (transformed or copied); Jc = Kc = 0.
@@ -42,6 +45,16 @@ __global__ void kb_prepare(const MolDesc *mols, int nset) {
         m.Jc[t] = 0.0;
         m.Kc[t] = 0.0;
     }
+    const int64_t njp = (int64_t)nset * m.njp;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < njp; t += (int64_t)gridDim.x * blockDim.x)
+        m.jp[t] = 0.0;
+}
+
+__global__ void kb_jp_scatter(const MolDesc *mols, int nset) {
+    const MolDesc &m = mols[blockIdx.y];
+    const int64_t nt = (int64_t)nset * m.npair * 64;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+        jp_scatter_elem(m.pairs, m.maps.l, m.jp, m.njp, m.Jc, (int64_t)m.naoc * m.naoc, m.naoc, m.npair, t);
 }
 
 __global__ void kb_dmax(const MolDesc *mols, int nset) {
@@ -91,6 +104,7 @@ struct jk_batch {
     int32_t *d_tasks = nullptr;  // row tasks of the row-kind descriptors
     int nctr = 0;
     int64_t max_elems = 0;      // largest nset * naoc^2 over the molecules
+    int64_t max_jpt = 0;        // largest nset * npair * 64 (scatter threads)
     int max_ns2 = 0;
     std::vector<void *> allocs;
     MolDesc *h_stage = nullptr;  // pinned staging for pointer updates
@@ -141,6 +155,8 @@ static int record(jk_batch *b) {
         else HIPCHK(e.batch[g.fam - 1][pr](b->d_desc + g.first, g.count, g.total_tiles, s));
         if (b->precision == JK_MIXED) HIPCHK(e.batch_list[g.fam64 - 1](b->d_desc + g.first, g.count, g.list_cap, s));
     }
+    hipLaunchKernelGGL(kb_jp_scatter, dim3(grid_rows(b->max_jpt), nm), dim3(256), 0, s, b->d_mol, b->nset);
+    HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(kb_finalize, dim3(grid_rows(b->max_elems), nm), dim3(256), 0, s, b->d_mol, b->nset);
     HIPCHK(hipGetLastError());
     return 0;
@@ -172,21 +188,24 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
     int rc;
 
     // per-molecule scratch, one allocation each kind
-    std::vector<int64_t> eoff(nmol + 1, 0), soff(nmol + 1, 0), loff(nmol + 1, 0), coff(nmol + 1, 0);
+    std::vector<int64_t> eoff(nmol + 1, 0), soff(nmol + 1, 0), loff(nmol + 1, 0), coff(nmol + 1, 0), joff(nmol + 1, 0);
     for (int m = 0; m < nmol; ++m) {
         const jk_plan *P = plans[m];
         const int64_t e = (int64_t)nset * P->naoc * P->naoc;
         eoff[m + 1] = eoff[m] + e;
+        joff[m + 1] = joff[m] + (int64_t)nset * P->njp;
+        b->max_jpt = std::max(b->max_jpt, (int64_t)nset * (int64_t)P->hpairs.size() * 64);
         soff[m + 1] = soff[m] + (int64_t)P->ns * P->ns;
         loff[m + 1] = loff[m] + 2 * std::max<int64_t>(P->stats.nquartets, 1);
         coff[m + 1] = coff[m] + (int64_t)P->cls.size();
         b->max_elems = std::max(b->max_elems, e);
         b->max_ns2 = std::max(b->max_ns2, P->ns * P->ns);
     }
-    double *Dc, *Jc, *Kc;
+    double *Dc, *Jc, *Kc, *jp;
     float *dmax = nullptr;
     int32_t *list = nullptr;
-    if ((rc = b->alloc(&Dc, eoff[nmol])) || (rc = b->alloc(&Jc, eoff[nmol])) || (rc = b->alloc(&Kc, eoff[nmol])))
+    if ((rc = b->alloc(&Dc, eoff[nmol])) || (rc = b->alloc(&Jc, eoff[nmol])) || (rc = b->alloc(&Kc, eoff[nmol])) ||
+        (rc = b->alloc(&jp, joff[nmol])))
         return rc;
     if (precision == JK_MIXED && ((rc = b->alloc(&dmax, soff[nmol])) || (rc = b->alloc(&list, loff[nmol])))) return rc;
 
@@ -208,6 +227,10 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         md.Dc = Dc + eoff[m];
         md.Jc = Jc + eoff[m];
         md.Kc = Kc + eoff[m];
+        md.jp = jp + joff[m];
+        md.pairs = P->d_pairs;
+        md.njp = P->njp;
+        md.npair = (int32_t)P->hpairs.size();
         md.dmax = dmax ? dmax + soff[m] : nullptr;
         md.nao = P->nao;
         md.naoc = P->naoc;
@@ -243,6 +266,8 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             a.J = md.Jc;
             a.K = md.Kc;
             a.mstride = (int64_t)P->naoc * P->naoc;
+            a.jp = md.jp;
+            a.jpstride = P->njp;
             a.nao = P->naoc;
             a.nset = nset;
             a.do_j = 1;

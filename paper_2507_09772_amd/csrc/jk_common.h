@@ -36,7 +36,9 @@ struct PairRec {
     int32_t aoi, aoj;      // Cartesian AO offsets
     int32_t pp_off, npp;   // first primitive pair, count
     int32_t pp_stride;     // distance between its consecutive primitive pairs
-    int32_t pad1;
+                           // (= the number of pairs of its type)
+    int32_t jp_off;        // its first element in the pair-ordered J' buffer;
+                           // element e (= i * ncart(l_J) + j) at jp_off + e * pp_stride
     double ab[3];          // A - B
     double q;              // Schwarz factor sqrt(max |(ab|ab)|)
 };
@@ -122,6 +124,11 @@ struct JkArgs {
     const double *D;
     double *J, *K;
     int64_t mstride;
+    // J'_KL of the ket pairs, pair-ordered ([nset][jpstride], see PairRec):
+    // the lanes of a wave hold consecutive kets, so these atomics land on
+    // consecutive addresses; added into J after the class kernels
+    double *jp;
+    int64_t jpstride;
     int32_t nao, nset, do_j, do_k;
     // precision split
     const float *dmax;   // [nshell][nshell] max |D| over the block and densities

@@ -810,12 +810,15 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                     }
                 }
                 if (valid) {
+                    // J'_KL into the pair-ordered buffer (consecutive kets,
+                    // consecutive addresses)
+                    double *jq = a.jp + s * a.jpstride + Kt.jp_off;
 #pragma unroll
                     for (int cd2 = 0; cd2 < NCD; ++cd2) {
                         double s2 = 0.0;
 #pragma unroll
                         for (int ab2 = 0; ab2 < NAB; ++ab2) s2 += (double)V[ab2 * NCD + cd2] * dij[ab2];
-                        atomic_add_f64(&Jm[(Kt.aoi + cd2 / NL) * n + Kt.aoj + cd2 % NL], w2 * s2);
+                        atomic_add_f64(&jq[(int64_t)cd2 * Kt.pp_stride], w2 * s2);
                     }
                 }
             }
@@ -1020,13 +1023,13 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
                 for (int m = 0; m < NM; ++m)
                     if (lane + 64 * m < NAB) atomicAdd(&jij[lane + 64 * m], mine[m]);
                 if (valid) {
-                    double *Jm = a.J + s * a.mstride;
+                    double *jq = a.jp + s * a.jpstride + Kt.jp_off;
 #pragma unroll
                     for (int cd2 = 0; cd2 < NCD; ++cd2) {
                         double s2 = 0.0;
 #pragma unroll
                         for (int ab2 = 0; ab2 < NAB; ++ab2) s2 += (double)V[ab2 * NCD + cd2] * dij[ab2];
-                        atomic_add_f64(&Jm[(Kt.aoi + cd2 / NL) * n + Kt.aoj + cd2 % NL], w2 * s2);
+                        atomic_add_f64(&jq[(int64_t)cd2 * Kt.pp_stride], w2 * s2);
                     }
                 }
             }

@@ -39,6 +39,25 @@ struct AoMaps {
 // element functions of the basis transforms, shared by the single and the
 // batched builds
 // ---------------------------------------------------------------------------
+// Adds the pair-ordered J' buffer into the Cartesian J' (after the class
+// kernels): t = ((s * npair) + p) * 64 + lane; the lanes of one pair walk its
+// elements.  Pairs own disjoint blocks (rows of the first shell, columns of
+// the second), so plain adds suffice.
+__device__ __forceinline__ void jp_scatter_elem(const PairRec *__restrict__ pairs, const int32_t *__restrict__ lsh,
+                                                const double *__restrict__ jp, int64_t jpstride, double *Jc,
+                                                int64_t mstride, int naoc, int npair, int64_t t) {
+    const int e0 = (int)(t & 63);
+    const int64_t u = t >> 6;
+    const int p = (int)(u % npair);
+    const int64_t s = u / npair;
+    const PairRec &r = pairs[p];
+    const int nb = ncart(lsh[r.jsh]), nab = ncart(lsh[r.ish]) * nb;
+    for (int e = e0; e < nab; e += 64) {
+        const double v = jp[s * jpstride + r.jp_off + (int64_t)e * r.pp_stride];
+        if (v != 0.0) Jc[s * mstride + (int64_t)(r.aoi + e / nb) * naoc + r.aoj + e % nb] += v;
+    }
+}
+
 __device__ __forceinline__ const double *c2s_of(const AoMaps &m, int l) {
     return m.c2s + (l == 0 ? jkt_c2s_offset[0] : l == 1 ? jkt_c2s_offset[1] : l == 2 ? jkt_c2s_offset[2]
                     : l == 3 ? jkt_c2s_offset[3] : jkt_c2s_offset[4]);
@@ -150,6 +169,8 @@ struct jk_plan {
     AoMaps maps{};
     double *d_Jc = nullptr, *d_Kc = nullptr, *d_Dc = nullptr;
     int scratch_nset = 0, dc_nset = 0;
+    double *d_jp = nullptr;  // pair-ordered J'_KL buffer [scratch_nset][njp]
+    int64_t njp = 0;
     int32_t *d_list = nullptr, *d_list_cnt = nullptr;  // mixed split
     int32_t *d_tpos = nullptr;                         // shell -> index within its type
     bool last_mixed = false;
