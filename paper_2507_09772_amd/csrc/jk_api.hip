@@ -854,9 +854,12 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
         a.same = c.same;
         a.npb = c.npb;
         a.npk = c.npk;
-        const int pr = precision == JK_FP64 ? 0 : 1;
+        // mixed: only the one-root classes are split (their FP32 kernels read
+        // a third of the FP64 Boys row); the others run in FP64 throughout
+        const bool split = precision == JK_MIXED && mixed_split_class(c.li, c.lj, c.lk, c.ll);
+        const int pr = precision == JK_FP64 || (precision == JK_MIXED && !split) ? 0 : 1;
         const int f = c.fam[pr];
-        a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
+        a.sel = split ? SEL_LOW : SEL_ALL;
         a.list = P->d_list ? P->d_list + 2 * c.list_off : nullptr;
         a.list_count = P->d_list_cnt ? P->d_list_cnt + ci : nullptr;
         a.nq = (int32_t)c.nq;
@@ -907,7 +910,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
             if ((rc = mark(slot, longrows ? c.nq - c.nq_row : c.nq))) return rc;
             HIPCHK(e.tiles[f - 1][pr](a, s));
         }
-        if (precision == JK_MIXED) {
+        if (split) {
             // the FP32 passes above diverted large-bound quartets to the
             // list; the FP64 list pass follows
             const int f64 = c.fam[0];

@@ -81,6 +81,7 @@ __global__ void kb_zero_i32(int32_t *p, int n) {
 // group.
 struct Group {
     int cid, fam, fam64;
+    int pr, split;     // kernel precision (0 FP64, 1 FP32); mixed split with list pass
     int kind;          // 0: tiles, 1: 64-lane row tasks
     size_t lds;        // row tasks: largest dynamic LDS over the descriptors
     int first, count;
@@ -147,13 +148,12 @@ static int record(jk_batch *b) {
         hipLaunchKernelGGL(kb_dmax, dim3(grid_rows(b->max_ns2), nm), dim3(256), 0, s, b->d_mol, b->nset);
         HIPCHK(hipGetLastError());
     }
-    const int pr = b->precision == JK_FP64 ? 0 : 1;
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const Group &g = b->groups[gi];
         const ClassEntry &e = g_classes[g.cid];
-        if (g.kind == 1) HIPCHK(e.batch_row[g.fam - 1][pr](b->d_desc + g.first, g.count, g.total_tiles, g.lds, s));
-        else HIPCHK(e.batch[g.fam - 1][pr](b->d_desc + g.first, g.count, g.total_tiles, s));
-        if (b->precision == JK_MIXED) HIPCHK(e.batch_list[g.fam64 - 1](b->d_desc + g.first, g.count, g.list_cap, s));
+        if (g.kind == 1) HIPCHK(e.batch_row[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, g.lds, s));
+        else HIPCHK(e.batch[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, s));
+        if (g.split) HIPCHK(e.batch_list[g.fam64 - 1](b->d_desc + g.first, g.count, g.list_cap, s));
     }
     hipLaunchKernelGGL(kb_jp_scatter, dim3(grid_rows(b->max_jpt), nm), dim3(256), 0, s, b->d_mol, b->nset);
     HIPCHK(hipGetLastError());
@@ -213,10 +213,10 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
     // Unless row mode is off for the class, every bra runs as 64-lane row
     // tasks (K rows in LDS): the small molecules of a batch have few long
     // bras, and per-quartet K atomics would dominate.
-    const int pr = precision == JK_FP64 ? 0 : 1;
-    std::map<std::tuple<int, int, int, int>, std::vector<std::pair<double, BatchDesc>>> byg;
+    using Key = std::tuple<int, int, int, int, int, int>;  // class, family, FP64 family, kind, precision, split
+    std::map<Key, std::vector<std::pair<double, BatchDesc>>> byg;
     std::vector<int32_t> alltasks;
-    std::map<std::tuple<int, int, int, int>, size_t> glds;
+    std::map<Key, size_t> glds;
     b->hmol.resize(nmol);
     for (int m = 0; m < nmol; ++m) {
         const jk_plan *P = plans[m];
@@ -238,6 +238,9 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         md.sph = P->sph;
         for (size_t ci = 0; ci < P->cls.size(); ++ci) {
             const ClassTask &c = P->cls[ci];
+            // mixed: only the one-root classes are split (as in jk_execute)
+            const bool split = precision == JK_MIXED && mixed_split_class(c.li, c.lj, c.lk, c.ll);
+            const int pr = precision == JK_FP64 || (precision == JK_MIXED && !split) ? 0 : 1;
             const int f = c.fam[pr];
             if (c.ntiles[f - 1] <= 0) continue;
             const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
@@ -274,7 +277,7 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             a.do_k = 1;
             a.dmax = md.dmax;
             a.nshell = P->ns;
-            a.sel = precision == JK_MIXED ? SEL_LOW : SEL_ALL;
+            a.sel = split ? SEL_LOW : SEL_ALL;
             a.mix_thr = mix_threshold;
             a.tab = P->tab;
             d.pad[0] = (int32_t)(coff[m] + (int64_t)ci);  // list counter slot (host only)
@@ -294,9 +297,9 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
                 a.seg_same = c.seg_same;
                 if (alltasks.size() > (size_t)INT32_MAX) return fail(JK_EINVAL, "too many row tasks");
             }
-            if (!(kind == 1 || ce.batch[f - 1][pr]) || (precision == JK_MIXED && !ce.batch_list[c.fam[0] - 1]))
+            if (!(kind == 1 || ce.batch[f - 1][pr]) || (split && !ce.batch_list[c.fam[0] - 1]))
                 return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has no batched kernel", c.li, c.lj, c.lk, c.ll);
-            const auto key = std::make_tuple(class_id(c.li, c.lj, c.lk, c.ll), f, c.fam[0], kind);
+            const Key key = std::make_tuple(class_id(c.li, c.lj, c.lk, c.ll), f, c.fam[0], kind, pr, split ? 1 : 0);
             byg[key].push_back({c.flops, d});
             if (kind == 1) glds[key] = std::max(glds[key], lds1);
         }
@@ -309,6 +312,8 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         g.fam = std::get<1>(kv.first);
         g.fam64 = std::get<2>(kv.first);
         g.kind = std::get<3>(kv.first);
+        g.pr = std::get<4>(kv.first);
+        g.split = std::get<5>(kv.first);
         g.lds = g.kind == 1 ? glds[kv.first] : 0;
         g.first = (int)b->hdesc.size();
         g.count = (int)v.size();

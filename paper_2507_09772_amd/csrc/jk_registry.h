@@ -35,6 +35,12 @@ inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj
            sizeof(double) * (size_t)nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj));
 }
 
+// Classes whose quartets the mixed precision mode splits into FP32 and FP64
+// (the rest it computes in FP64): on this chip single-precision vector
+// arithmetic runs at the FP64 rate, so only the one-root classes, bound by
+// their Boys-table gathers (20 bytes per lane in FP32 against 64), gain.
+inline bool mixed_split_class(int li, int lj, int lk, int ll) { return nroots(li, lj, lk, ll) == 1; }
+
 // LDS budget of one row-mode workgroup (dynamic shared memory; gfx950 has
 // 160 KB per CU, kernels above 64 KB opt in through a function attribute).
 constexpr int ROW_LDS_MAX = 128 * 1024;
