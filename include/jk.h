@@ -50,7 +50,10 @@ enum {
 enum {
     JK_FP64 = 0,   /* every quartet in FP64 */
     JK_MIXED = 1,  /* quartets whose bound Q_IJ Q_KL max|D_block| < mix_threshold in
-                      FP32, the rest in FP64; accumulation always FP64 */
+                      FP32, the rest in FP64; accumulation always FP64.  On gfx950
+                      only the one-root classes ((ss|ss), (ps|ss)) are split: single
+                      precision gains nothing elsewhere, so the other classes run
+                      in FP64 throughout */
     JK_FP32 = 2    /* every quartet in FP32, FP64 accumulation */
 };
 
@@ -85,7 +88,8 @@ typedef struct jk_batch jk_batch;
 typedef struct {
     int64_t nquartets;          /* significant unique shell quartets */
     int64_t nprim_quartets;     /* primitive quartets inside them */
-    int64_t nquartets_fp32;     /* quartets run in FP32 by the last JK_MIXED execute */
+    int64_t nquartets_fp32;     /* quartets run in FP32 by the last JK_MIXED execute
+                                   (split classes only) */
     int32_t nclasses;           /* (bra pair type, ket pair type) launches */
     int32_t npairs;             /* shell pairs kept after screening */
     double setup_ms;            /* jk_plan_create wall time */

@@ -621,9 +621,14 @@ extern "C" int jk_plan_stats(const jk_plan *P, jk_stats *st) {
         std::vector<int32_t> cnt(P->cls.size());
         HIPCHK(hipDeviceSynchronize());
         HIPCHK(hipMemcpy(cnt.data(), P->d_list_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost));
-        int64_t n64 = 0;
-        for (int32_t v : cnt) n64 += v;
-        st->nquartets_fp32 = P->stats.nquartets - n64;
+        // split classes only: their quartets minus those diverted to the
+        // FP64 list (the other classes run in FP64 throughout)
+        int64_t n32 = 0;
+        for (size_t ci = 0; ci < P->cls.size(); ++ci) {
+            const ClassTask &c = P->cls[ci];
+            if (mixed_split_class(c.li, c.lj, c.lk, c.ll)) n32 += c.nq - cnt[ci];
+        }
+        st->nquartets_fp32 = n32;
     }
     return 0;
 }
