@@ -231,6 +231,10 @@ def test_mixed_small(jkmod, torch_cuda, basis, nw):
     ej, ek = o.energies(wl.D, J, K)
     assert abs(ej[0] - ej0[0]) <= 1e-6 and abs(ek[0] - ek0[0]) <= 1e-6
     assert np.abs(J - J0).max() <= 1e-6 and np.abs(K - K0).max() <= 1e-6
+    # only the one-root classes are split, and some of their quartets are
+    # far enough for FP32
+    st = plan.stats()
+    assert 0 < st.nquartets_fp32 < st.nquartets
     _, J32, K32 = run_gpu(jkmod, torch_cuda, wl, precision="fp32", plan=plan)
     assert np.abs(J32 - J0).max() <= 1e-3
 
