@@ -620,7 +620,8 @@ __device__ __forceinline__ PQuart<R> prim_quartet(const PrimPair &pb, const Prim
 // ===========================================================================
 // Family 1: one lane per quartet.  The contracted Cartesian block V lives in
 // registers; digestion reduces J_IJ across the wave when the bra is uniform
-// (tiles) and sends the other blocks straight to FP64 atomics.
+// (tiles), adds J_KL into the pair-ordered buffer and sends the K blocks
+// straight to FP64 atomics.
 // ===========================================================================
 // Waits for the loads of a record here, once: values that are still
 // loading at the top of a loop make the compiler wait for every load issued
@@ -955,8 +956,8 @@ __device__ __forceinline__ int batch_desc(const BatchDesc *__restrict__ d, int n
 // Row mode: one workgroup of NT lanes walks a chunk of one bra's ket prefix
 // (a row task: list position, first and end ket).  K'_IK, K'_IL (row block
 // of shell I) and K'_JK, K'_JL (row block of J) accumulate in LDS over the
-// compressed ket-type columns, J'_IJ in LDS, and only J'_KL goes to global
-// atomics per quartet.  Dynamic LDS layout: the bra's npb primitive pair
+// compressed ket-type columns, J'_IJ in LDS, and only J'_KL leaves per
+// quartet (atomics into the pair-ordered buffer).  Dynamic LDS layout: the bra's npb primitive pair
 // records, then per density [NI rows | NJ rows] x ncols and NAB for J'_IJ.
 // NT = 256 for long bras, 64 for short ones;
 // BATCH: the task indexes the row tasks of many descriptors (molecules).
