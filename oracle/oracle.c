@@ -493,8 +493,8 @@ static void load_c2s(double store[OR_LMAX + 1][OR_MAXNC * (2 * OR_LMAX + 1)], co
  * shell-pair level like the Schwarz test): with dscreen > 0 a quartet is
  * kept only if Q_IJ Q_KL max(Dm_IJ, Dm_KL, Dm_IK, Dm_IL, Dm_JK, Dm_JL) >=
  * dscreen, Dm_XY = max over densities and the Cartesian components of the
- * block (X, Y) of |D| (the Cartesian density, single precision, the
- * precision the GPU library takes this decision in).  Applied to a density
+ * block (X, Y) of |D| (the Cartesian density, double precision).  Applied
+ * to a density
  * change Delta D this is the incremental-SCF screening; it bounds every
  * dropped contribution to J and K by dscreen.
  */
@@ -507,7 +507,7 @@ static double *dmax_table(const obasis *b, const double *Dc, int nset) {
             for (int s = 0; s < nset; ++s)
                 for (int a = b->coff[I]; a < b->coff[I + 1]; ++a)
                     for (int c = b->coff[J]; c < b->coff[J + 1]; ++c) m = fmax(m, fabs(Dc[(size_t)s * nc * nc + (size_t)a * nc + c]));
-            dm[I * ns + J] = (double)(float)m;
+            dm[I * ns + J] = m;
         }
     return dm;
 }
@@ -649,6 +649,59 @@ int oracle_jk_screen(BASIS_ARGS, double omega, double dscreen, const double *D, 
     }
     if (nsig) *nsig = count;
     free(dm); free(Q); free(Dc); free(Jc); free(Kc); ob_free(&b);
+    return 0;
+}
+
+/*
+ * Mixed-precision classification (the split of the benchmark's config 3, a
+ * reading of the paper's mixed-precision outlook in Section 6): over the
+ * unique quartets I>=J, K>=L, IJ>=KL that pass the Schwarz test, count
+ * those whose bound Q_IJ Q_KL max(Dm_IJ, Dm_KL, Dm_IK, Dm_IL, Dm_JK, Dm_JL)
+ * is below thr (they may run in single precision).  Dm as in the density
+ * screening above (FP64 block maxima of the Cartesian density).
+ */
+int oracle_mixed_count(BASIS_ARGS, const double *D, int nset, double cutoff, double thr, const double *Qin,
+                       long long *nsig, long long *nlow) {
+    obasis b;
+    if (ob_init(&b, BASIS_PASS)) return -1;
+    const int ns_ = b.ns, nc = b.nao_cart, ne = b.nao_ext;
+    double c2s_store[OR_LMAX + 1][OR_MAXNC * (2 * OR_LMAX + 1)];
+    const double *Tl[OR_LMAX + 1];
+    load_c2s(c2s_store, Tl);
+    double *Q = (double *)malloc(sizeof(double) * ns_ * ns_);
+    if (Qin) memcpy(Q, Qin, sizeof(double) * ns_ * ns_); else schwarz(&b, Q);
+    double *Dc = (double *)malloc(sizeof(double) * nset * nc * nc);
+    for (int s = 0; s < nset; ++s) d_to_cart(&b, D + (size_t)s * ne * ne, Dc + (size_t)s * nc * nc, Tl);
+    double *dm = dmax_table(&b, Dc, nset);
+    const int npair = ns_ * (ns_ + 1) / 2;
+    long long cs = 0, cl = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : cs, cl)
+    for (int ij = 0; ij < npair; ++ij) {
+        int I = (int)((sqrt(8.0 * ij + 1.0) - 1.0) / 2.0);
+        while (I * (I + 1) / 2 > ij) --I;
+        while ((I + 1) * (I + 2) / 2 <= ij) ++I;
+        const int J = ij - I * (I + 1) / 2;
+        for (int kl = 0; kl <= ij; ++kl) {
+            int K = (int)((sqrt(8.0 * kl + 1.0) - 1.0) / 2.0);
+            while (K * (K + 1) / 2 > kl) --K;
+            while ((K + 1) * (K + 2) / 2 <= kl) ++K;
+            const int L = kl - K * (K + 1) / 2;
+            const double qq = Q[I * ns_ + J] * Q[K * ns_ + L];
+            if (qq < cutoff) continue;
+            ++cs;
+            double m = dm[I * ns_ + J];
+            m = fmax(m, dm[K * ns_ + L]);
+            m = fmax(m, dm[I * ns_ + K]);
+            m = fmax(m, dm[I * ns_ + L]);
+            m = fmax(m, dm[J * ns_ + K]);
+            m = fmax(m, dm[J * ns_ + L]);
+            if (qq * m < thr) ++cl;
+        }
+    }
+    *nsig = cs;
+    *nlow = cl;
+    free(dm); free(Dc); free(Q);
+    ob_free(&b);
     return 0;
 }
 

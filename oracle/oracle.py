@@ -13,6 +13,8 @@ Parity status of each function (pins in tests/test_oracle_*.py):
               0 <= Tr(DK) <= Tr(DJ), rotation / translation invariance,
               linearity in D
   jk_blocks   pinned: equals the corresponding blocks of jk
+  mixed_count pinned: its significant count equals jk's; its FP32 count
+              equals a brute-force count over every ordered quartet in numpy
   c2s         pinned: orthonormality, harmonicity, agreement with an
               independent least-squares projection of spherical harmonics
 """
@@ -149,6 +151,25 @@ def jk(mol, D: np.ndarray, cutoff: float = 1e-13, mode: int = 1, Q: np.ndarray |
     if rc:
         raise ValueError("invalid basis")
     return J, K, int(cnt.value)
+
+
+def mixed_count(mol, D: np.ndarray, cutoff: float = 1e-13, thr: float = 1e-4, Q: np.ndarray | None = None):
+    """(significant unique quartets, those whose bound Q_IJ Q_KL max|D_block|
+    over the six blocks is below thr): the mixed-precision split's count."""
+    b = _Basis(mol)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    if D.ndim == 2:
+        D = D[None]
+    qp = None
+    if Q is not None:
+        Qc = np.ascontiguousarray(Q, dtype=np.float64)
+        qp = _dp(Qc)
+    ns, nl = ctypes.c_longlong(), ctypes.c_longlong()
+    rc = _load().oracle_mixed_count(*b.args(), _dp(D), ctypes.c_int(D.shape[0]), ctypes.c_double(cutoff),
+                                    ctypes.c_double(thr), qp, ctypes.byref(ns), ctypes.byref(nl))
+    if rc:
+        raise ValueError("invalid basis")
+    return int(ns.value), int(nl.value)
 
 
 def jk_blocks(mol, D: np.ndarray, Q: np.ndarray, jpairs, kpairs, cutoff: float = 1e-13):

@@ -1,7 +1,7 @@
 """Pins of the oracle's density screening (direct-SCF screening by the
 density matrix at shell-pair level, Section 2): a quartet is kept when
 Q_IJ Q_KL max(Dm_IJ, Dm_KL, Dm_IK, Dm_IL, Dm_JK, Dm_JL) >= dscreen, with Dm
-the single-precision block maxima of |D| over the Cartesian density.
+the block maxima of |D| over the Cartesian density (double precision).
 
 The reference here is a separate brute-force J/K in numpy over every ordered
 shell quartet (blocks from the pinned oracle ERI), with the screening rule
@@ -21,7 +21,7 @@ def brute_jk_screened(mol, D, cutoff, dscreen):
     dm = np.zeros((ns, ns))
     for I in range(ns):
         for J in range(ns):
-            dm[I, J] = float(np.float32(np.abs(D[off[I]:off[I + 1], off[J]:off[J + 1]]).max()))
+            dm[I, J] = float(np.abs(D[off[I]:off[I + 1], off[J]:off[J + 1]]).max())
     J_ = np.zeros_like(D)
     K_ = np.zeros_like(D)
     kept = dropped = 0
@@ -73,3 +73,43 @@ def test_zero_threshold_and_bound():
         # Cartesian element, each below thr; J' and K' are then symmetrised
         bound = 2 * 8 * (n0 - n) * thr
         assert np.abs(J - J0).max() <= bound and np.abs(K - K0).max() <= bound
+
+
+@pytest.mark.parametrize("basis,nw,thr", [("A", 3, 1e-4), ("B", 2, 1e-4), ("A", 2, 1e-6)])
+def test_mixed_count_brute_force(basis, nw, thr):
+    """The mixed-precision split count: significant unique quartets as in jk,
+    and those with Q_IJ Q_KL max|D| over the six blocks below thr, counted
+    here by a plain loop over the canonical quartets in numpy."""
+    wl = synth.small_workload(nw, basis, seed=17 + nw)
+    mol, D = wl.mol, wl.D
+    ns = mol.nshell
+    Q = o.schwarz(mol)
+    # Cartesian density blocks (spherical bases: D_cart = T^T D T per shell)
+    if mol.spherical:
+        T = [o.c2s(l) for l in range(4)]
+        offe = mol.ao_offsets()
+        nc = [(int(l) + 1) * (int(l) + 2) // 2 for l in mol.l]
+        offc = np.concatenate([[0], np.cumsum(nc)])
+        Dc = np.zeros((D.shape[0], offc[-1], offc[-1]))
+        for I in range(ns):
+            for J in range(ns):
+                Dc[:, offc[I]:offc[I + 1], offc[J]:offc[J + 1]] = np.einsum(
+                    "ma,smn,nb->sab", T[mol.l[I]], D[:, offe[I]:offe[I + 1], offe[J]:offe[J + 1]], T[mol.l[J]])
+    else:
+        Dc, offc = D, mol.ao_offsets()
+    dm = np.array([[np.abs(Dc[:, offc[I]:offc[I + 1], offc[J]:offc[J + 1]]).max() for J in range(ns)]
+                   for I in range(ns)])
+    pairs = [(I, J) for I in range(ns) for J in range(I + 1)]
+    nsig = nlow = 0
+    for a, (I, J) in enumerate(pairs):
+        for (K, L) in pairs[:a + 1]:
+            qq = Q[I, J] * Q[K, L]
+            if qq < 1e-13:
+                continue
+            nsig += 1
+            if qq * max(dm[I, J], dm[K, L], dm[I, K], dm[I, L], dm[J, K], dm[J, L]) < thr:
+                nlow += 1
+    got = o.mixed_count(mol, D, 1e-13, thr)
+    assert got == (nsig, nlow)
+    assert got[0] == o.jk(mol, D, 1e-13)[2]
+    assert 0 < nlow < nsig

@@ -79,7 +79,9 @@ def test_ssss_general_closed_form():
 # tensor Gauss-Hermite quadrature on the principal axes; the t integral is
 # done numerically.  No Boys function and no recurrence is involved.
 # ---------------------------------------------------------------------------
-_GH_X, _GH_W = np.polynomial.hermite.hermgauss(8)
+# 10 nodes per axis integrate polynomials up to degree 19 exactly: enough
+# for every Cartesian product up to (gg|gg) (degree 16 along one axis).
+_GH_X, _GH_W = np.polynomial.hermite.hermgauss(10)
 
 
 def _direction_integral(t, al, ce, pw):
@@ -110,9 +112,13 @@ def eri_quadrature(al, centers, powers):
     return 2.0 / math.sqrt(math.pi) * val
 
 
-@pytest.mark.parametrize("ls", [(0, 0, 0, 0), (1, 0, 0, 0), (1, 1, 0, 0), (1, 0, 1, 0), (1, 1, 1, 1), (2, 1, 0, 1)])
+@pytest.mark.parametrize("ls", [(0, 0, 0, 0), (1, 0, 0, 0), (1, 1, 0, 0), (1, 0, 1, 0), (1, 1, 1, 1), (2, 1, 0, 1),
+                                (3, 0, 0, 0), (0, 0, 0, 3), (3, 1, 2, 0), (2, 2, 2, 2), (3, 3, 1, 1), (1, 3, 3, 2),
+                                (3, 3, 3, 3)])
 def test_primitive_eri_vs_quadrature(ls):
-    rng = np.random.default_rng(100 + sum(ls))
+    """Every (li lj|lk ll) pattern the configurations reach up to (ff|ff),
+    with the f shells in every position, against brute-force quadrature."""
+    rng = np.random.default_rng(100 + sum(ls) + 7 * ls[0] + 3 * ls[3])
     C = rng.uniform(-1.5, 1.5, size=(4, 3))
     ex = np.exp(rng.uniform(math.log(0.2), math.log(5), size=4))
     mol = prim_molecule(C, [(ls[i], ex[i], 1.0, i) for i in range(4)])
@@ -188,3 +194,82 @@ def test_scaling_law(c0):
     for (I, J, K, L) in qs.values():
         np.testing.assert_allclose(o.eri_block(mol2, I, J, K, L) * lam, o.eri_block(mol, I, J, K, L),
                                    rtol=1e-12, atol=1e-16)
+
+
+# ---------------------------------------------------------------------------
+# the same pins on a molecule of the spherical triple-zeta-shaped basis,
+# whose quartets reach f shells in every position
+# ---------------------------------------------------------------------------
+def _quartets_by_l_sampled(mol, want, seed=0):
+    """One shell quartet per wanted (li, lj, lk, ll) pattern, on at least
+    three distinct atoms, by random draws over the shells of each l."""
+    rng = np.random.default_rng(seed)
+    by_l = {}
+    for i, l in enumerate(int(x) for x in mol.l):
+        by_l.setdefault(l, []).append(i)
+    out = {}
+    for key in sorted(want):
+        for _ in range(2000):
+            q = tuple(int(rng.choice(by_l[l])) for l in key)
+            if len({int(mol.atom[x]) for x in q}) > 2:
+                out[key] = q
+                break
+    return out
+
+
+@pytest.fixture(scope="module")
+def wat_b():
+    wl = synth.small_workload(3, "B", seed=31)
+    mol = wl.mol
+    # Cartesian blocks: the ERI pins concern the Cartesian integrals
+    return synth.Molecule(l=mol.l, nprim=mol.nprim, atom=mol.atom, exps=mol.exps, coefs=mol.coefs,
+                          coords=mol.coords, spherical=False)
+
+
+_F_KEYS = {(3, 0, 0, 0), (3, 2, 1, 0), (3, 3, 1, 1), (1, 3, 3, 2), (3, 3, 3, 3), (2, 3, 0, 3), (3, 1, 3, 1)}
+
+
+def test_eightfold_symmetry_f_shells(wat_b):
+    mol = wat_b
+    qs = _quartets_by_l_sampled(mol, _F_KEYS)
+    assert len(qs) == len(_F_KEYS)
+    for (I, J, K, L) in qs.values():
+        v = o.eri_block(mol, I, J, K, L)
+        tol = dict(rtol=1e-12, atol=1e-14 * max(1.0, np.abs(v).max()))
+        np.testing.assert_allclose(o.eri_block(mol, J, I, K, L), v.transpose(1, 0, 2, 3), **tol)
+        np.testing.assert_allclose(o.eri_block(mol, I, J, L, K), v.transpose(0, 1, 3, 2), **tol)
+        np.testing.assert_allclose(o.eri_block(mol, K, L, I, J), v.transpose(2, 3, 0, 1), **tol)
+        np.testing.assert_allclose(o.eri_block(mol, L, K, J, I), v.transpose(3, 2, 1, 0), **tol)
+
+
+def test_schwarz_bound_f_shells(wat_b):
+    mol = wat_b
+    Q = o.schwarz(mol)
+    ls = [int(x) for x in mol.l]
+    f = [i for i, l in enumerate(ls) if l == 3]
+    assert f
+    for I in f:
+        for J in range(mol.nshell):
+            d = o.eri_block(mol, I, J, I, J)
+            nab = d.shape[0] * d.shape[1]
+            diag = np.diag(d.reshape(nab, nab))
+            assert np.all(diag >= 0)
+            assert math.sqrt(diag.max()) == pytest.approx(Q[I, J], rel=1e-14)
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        I, J, K = (int(x) for x in rng.integers(0, mol.nshell, size=3))
+        L = f[int(rng.integers(len(f)))]
+        v = o.eri_block(mol, I, J, K, L)
+        assert np.abs(v).max() <= Q[I, J] * Q[K, L] * (1 + 1e-12)
+
+
+def test_scaling_law_f_shells(wat_b):
+    mol = wat_b
+    lam = 0.83
+    lpp = np.repeat(mol.l, mol.nprim)
+    mol2 = synth.Molecule(l=mol.l, nprim=mol.nprim, atom=mol.atom, exps=mol.exps / lam ** 2,
+                          coefs=mol.coefs * lam ** (-(lpp + 1.5)), coords=mol.coords * lam, spherical=False)
+    for (I, J, K, L) in _quartets_by_l_sampled(mol, _F_KEYS).values():
+        ref = o.eri_block(mol, I, J, K, L)
+        np.testing.assert_allclose(o.eri_block(mol2, I, J, K, L) * lam, ref, rtol=1e-12,
+                                   atol=1e-14 * max(1.0, np.abs(ref).max()))
