@@ -1,16 +1,28 @@
 #!/usr/bin/env python
 """J/K build benchmark on one MI355X.
 
-Workload (default): 64 waters on a 4x4x4 lattice, split-valence +
+Headline workload: 64 waters on a 4x4x4 lattice, split-valence +
 polarisation Cartesian basis (6-31G*-shaped), 1216 AOs, one density,
 Schwarz cutoff 1e-13.  Inputs are seeded and synthetic and resident in HBM
 before the timed region; a step is one full J+K build (every hot-path
 kernel: density transform when spherical, all class kernels, finalize).
 
-Prints one JSON line: FP64 builds/s as ``value``, ERI quartets/s, the mixed
-FP32/FP64 rate and its energy error against the FP64 GPU build, the
-roofline of the dominant kernel from HIP events over the timed region, and
-the CPU reference timed on a bounded sample.
+The same run measures every configuration of the workload set:
+  c1  the headline molecule, FP64 and mixed FP32/FP64;
+  c2  32 waters in the spherical triple-zeta-shaped basis up to f, FP64 and
+      mixed;
+  c3  the mixed-precision split (threshold 1e-4 on Q_IJ Q_KL max|D_block|)
+      on the c1 and c2 molecules: FP32 quartet fraction, speedup over FP64
+      and the error against the oracle's stored values;
+  c4  256 molecules of 1-8 waters with 4 densities each in one batched
+      build (recorded hipGraph), FP64 and mixed.
+Per build: builds/s and quartets/s from a plain timed loop (no per-kernel
+events), then a separate profiled pass (HIP events around every class
+kernel) for the per-kernel breakdown and the dominant kernel's roofline.
+Errors are taken against the oracle's stored values (tests/golden/, written
+by the oracle alone).  The CPU oracle is timed on a bounded sample.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -26,7 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "J/K builds/s + ERI quartets/s, FP64 vs mixed FP32/FP64 at |dE|<=1e-6 Eh"
 PEAK_FP64_VECTOR = 78.6   # TFLOP/s, MI355X FP64 vector
-PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X FP32 vector
+PEAK_FP32_VECTOR = 157.3  # TFLOP/s, MI355X FP32 vector (published, packed issue)
 
 WORKLOAD_TEXT = {
     "c0": "3 waters, basis A (6-31G*-shaped, Cartesian), 57 AOs, 1 density, cutoff 1e-13",
@@ -35,9 +47,13 @@ WORKLOAD_TEXT = {
 }
 BATCH_TEXT = ("256 molecules of 1-8 waters, half basis A (Cartesian), half basis B (spherical), "
               "4 densities each, cutoff 1e-13")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+COUNTERS = {"c1": os.path.join(ROOT, "profiles", "jk_c1_fp64_hbm_counters.txt"),
+            "c2": os.path.join(ROOT, "profiles", "jk_c2_fp64_hbm_counters.txt")}
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "jk_c1_fp64_hbm_counters.txt")
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def source_sha256():
@@ -56,14 +72,15 @@ def source_sha256():
     return h.hexdigest()
 
 
-def hbm_traffic(kernel: str):
+def hbm_traffic(workload: str, kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by the
     copy-kernel calibration), or (None, reason) when the summary is missing,
     does not cover the kernel, or was taken from other kernel sources."""
-    if not os.path.exists(COUNTERS):
-        return None, "no counter summary"
-    text = open(COUNTERS).read()
+    path = COUNTERS.get(workload)
+    if not path or not os.path.exists(path):
+        return None, "no counter summary for this workload"
+    text = open(path).read()
     m = re.search(r"kernel sources sha256[^:]*: ([0-9a-f]+)", text)
     if not m or m.group(1) != source_sha256():
         return None, "kernel sources changed since the counters were taken"
@@ -77,28 +94,36 @@ def hbm_traffic(kernel: str):
         return None, "kernel not in the counter summary"
     fetch = got["FETCH_SIZE"] * float(cal.group(1)) * 1024
     write = got["WRITE_SIZE"] * float(cal.group(2)) * 1024
-    return fetch + write, f"rocprofv3 FETCH_SIZE+WRITE_SIZE per dispatch, {os.path.relpath(COUNTERS, ROOT)}"
+    return fetch + write, f"rocprofv3 FETCH_SIZE+WRITE_SIZE per dispatch, {os.path.relpath(path, ROOT)}"
 
 
-def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+def golden(name):
+    with open(os.path.join(GOLDEN, f"{name}_jk.json")) as f:
+        return json.load(f)
 
 
-def timed_steps(plan, D, J, K, precision, steps, warmup, torch, profile=False):
+def timed_loop(run, steps, warmup, torch):
+    """Mean seconds per call of run() over `steps` calls after `warmup`,
+    bracketed by device synchronisations; nothing else in the loop."""
     for _ in range(warmup):
-        plan.execute(D, J, K, precision=precision)
+        run()
     torch.cuda.synchronize()
-    if profile:
-        plan.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        plan.execute(D, J, K, precision=precision)
+        run()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    tim = plan.timings() if profile else []
-    if profile:
-        plan.profile(False)
-    return dt, tim
+    return (time.perf_counter() - t0) / steps
+
+
+def profiled(plan, run, steps, torch):
+    """Per-launch HIP-event timings of `steps` builds (a separate pass)."""
+    plan.profile(True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    tim = plan.timings()
+    plan.profile(False)
+    return tim
 
 
 def kernel_name(t):
@@ -108,17 +133,232 @@ def kernel_name(t):
     cls = f"{t.li}, {t.lj}, {t.lk}, {t.ll}"
     if t.kind in (1, 3):
         return f"jk_k{t.family}_row<{cls}, {prec}, {256 if t.kind == 1 else 64}, false>"
-    return f"jk_k{t.family}<{cls}, {prec}, {0 if t.kind == 0 else 2}>"
+    return f"jk_k{t.family}<{cls}, {prec}, 0>"
 
 
 def kernel_groups(timings):
     out = {}
     for t in timings:
-        g = out.setdefault(kernel_name(t), {"ms": 0.0, "launches": 0, "flops": 0.0, "quartets": 0})
+        g = out.setdefault(kernel_name(t), {"ms": 0.0, "launches": 0, "flops": 0.0, "quartets": 0,
+                                            "precision": "fp64" if t.precision == 0 else "fp32"})
         g["ms"] += t.ms
         g["launches"] += t.launches
         g["flops"] += t.model_flops
         g["quartets"] += t.nquartets
+    return out
+
+
+def roofline_of(workload, kern, steps):
+    """Dominant kernel (most time) of a profiled pass, against the vector
+    peak of its precision."""
+    name, k = max(kern.items(), key=lambda kv: kv[1]["ms"])
+    peak = PEAK_FP64_VECTOR if k["precision"] == "fp64" else PEAK_FP32_VECTOR
+    achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12
+    traffic, src = hbm_traffic(workload, name)
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": traffic, "traffic_source": src, "kernel": name, "avg_launch_ms": k["ms"] / k["launches"],
+            "launches_per_build": k["launches"] / steps, "model_flops_per_launch": k["flops"] / k["launches"]}
+
+
+def errors_vs_golden(g, D, J, K):
+    """max |dJ|, |dK| over the stored elements and dE_J, dE_K (closed-shell
+    reading E_J = 2 Tr(DJ), E_K = Tr(DK)) against the oracle's values."""
+    import numpy as np
+    Jh, Kh, Dh = J[0].cpu().numpy(), K[0].cpu().numpy(), D[0]
+    ej, ek = 2.0 * float(np.sum(Dh * Jh)), float(np.sum(Dh * Kh))
+    return {"max_dJ": float(np.abs(Jh.ravel()[::g["stride"]] - np.asarray(g["J"])).max()),
+            "max_dK": float(np.abs(Kh.ravel()[::g["stride"]] - np.asarray(g["K"])).max()),
+            "dE_J": ej - g["E_J"], "dE_K": ek - g["E_K"], "E_J": ej, "E_K": ek}
+
+
+def bench_molecule(name, args, torch, jk, synth, steps, warmup):
+    """FP64 and mixed builds of one molecule: timed loop, profiled pass,
+    errors against the oracle's stored values."""
+    wl = synth.workload(name)
+    g = golden(name)
+    t0 = time.perf_counter()
+    plan = jk.Plan(wl.mol, wl.cutoff)
+    st = plan.stats()
+    log(f"{name}: {wl.mol.nshell} shells, {wl.mol.nao} AOs; plan {time.perf_counter() - t0:.2f} s, "
+        f"{st.nquartets} quartets, {st.nprim_quartets} primitive quartets, {st.nclasses} classes")
+    D = torch.from_numpy(wl.D).cuda()
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+    psteps = max(1, min(steps, 5))
+    res = {"workload": f"{name}: {WORKLOAD_TEXT[name]}", "nquartets": st.nquartets,
+           "nprim_quartets": st.nprim_quartets, "plan_seconds": time.perf_counter() - t0,
+           "model_flops_per_build": st.model_flops, "steps": steps, "warmup": warmup}
+    for prec in ("fp64", "mixed"):
+        def run():
+            plan.execute(D, J, K, precision=prec, mix_threshold=args.mix_threshold)
+        dt = timed_loop(run, steps, warmup, torch)
+        err = errors_vs_golden(g, wl.D, J, K)
+        stp = plan.stats()
+        tim = profiled(plan, run, psteps, torch)
+        kern = kernel_groups(tim)
+        f64 = sum(k["flops"] for k in kern.values() if k["precision"] == "fp64") / psteps
+        f32 = sum(k["flops"] for k in kern.values() if k["precision"] == "fp32") / psteps
+        ms64 = sum(k["ms"] for k in kern.values() if k["precision"] == "fp64") / psteps
+        ms32 = sum(k["ms"] for k in kern.values() if k["precision"] == "fp32") / psteps
+        t_bound = f64 / (PEAK_FP64_VECTOR * 1e12) + f32 / (PEAK_FP32_VECTOR * 1e12)
+        r = {"ms_per_step": dt * 1e3, "builds_per_s": 1.0 / dt, "quartets_per_s": st.nquartets / dt,
+             "prim_quartets_per_s": st.nprim_quartets / dt, "model_tflops": st.model_flops / dt / 1e12,
+             "frac_of_vector_roofline": t_bound / dt, "fp32_quartets": stp.nquartets_fp32,
+             "fp32_fraction": stp.nquartets_fp32 / st.nquartets, "kernel_ms_fp64": ms64, "kernel_ms_fp32": ms32,
+             "roofline": roofline_of(name, kern, psteps), "vs_oracle": err}
+        top = sorted(kern.items(), key=lambda kv: -kv[1]["ms"])[:args.top]
+        r["top_kernels"] = [{"kernel": n, "ms_per_build": k["ms"] / psteps,
+                             "tflops": k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0}
+                            for n, k in top]
+        log(f"{name} {prec}: {dt * 1e3:.2f} ms/build, {st.nquartets / dt:.3e} quartets/s, fp32 fraction "
+            f"{r['fp32_fraction']:.3f}; kernels fp64 {ms64:.1f} ms fp32 {ms32:.1f} ms; vs oracle max|dJ| "
+            f"{err['max_dJ']:.1e} max|dK| {err['max_dK']:.1e} dE_J {err['dE_J']:.1e} dE_K {err['dE_K']:.1e}")
+        for n, k in top:
+            log(f"  {n:46s} {k['ms'] / psteps:8.3f} ms/build  {k['launches'] / psteps:4.0f} launches  "
+                f"{k['flops'] / (k['ms'] * 1e-3) / 1e12 if k['ms'] > 0 else 0:6.2f} TF/s")
+        res[prec] = r
+    res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    if name == "c1" and not args.no_dscreen:
+        res["density_screening"] = bench_dscreen(args, torch, plan, wl, res["fp64"]["ms_per_step"] * 1e-3, steps,
+                                                 warmup)
+    plan.close()
+    return res
+
+
+def bench_batch(args, torch, jk, synth, steps, warmup):
+    """Batched builds over the 256-molecule set (one graph replay per step),
+    FP64 and mixed, against the oracle's stored per-molecule values, and the
+    same molecules built one jk_execute at a time."""
+    import numpy as np
+    wls = synth.batch_workload()
+    g = golden("c4")
+    t0 = time.perf_counter()
+    plans = [jk.Plan(w.mol, w.cutoff) for w in wls]
+    t_plan = time.perf_counter() - t0
+    Ds = [torch.from_numpy(w.D).cuda() for w in wls]
+    Js = [torch.empty_like(D) for D in Ds]
+    Ks = [torch.empty_like(D) for D in Ds]
+    nset = Ds[0].shape[0]
+    nq = sum(p.stats().nquartets for p in plans)
+    res = {"workload": f"c4: {BATCH_TEXT}", "nmol": len(wls), "nset": nset, "plan_seconds": t_plan,
+           "nquartets": nq, "steps": steps, "warmup": warmup}
+    log(f"c4: {len(wls)} plans in {t_plan:.1f} s, {nq} quartets")
+
+    def errors():
+        dj = dk = de = 0.0
+        for w, J, K, gm in zip(wls, Js, Ks, g["molecules"]):
+            Jh, Kh = J.cpu().numpy(), K.cpu().numpy()
+            dj = max(dj, float(np.abs(Jh.ravel()[::g["stride"]] - np.asarray(gm["J"])).max()))
+            dk = max(dk, float(np.abs(Kh.ravel()[::g["stride"]] - np.asarray(gm["K"])).max()))
+            ej = 2.0 * np.einsum("sij,sij->s", w.D, Jh)
+            ek = np.einsum("sij,sij->s", w.D, Kh)
+            de = max(de, float(np.abs(ej - np.asarray(gm["E_J"])).max()), float(np.abs(ek - np.asarray(gm["E_K"])).max()))
+        return {"max_dJ": dj, "max_dK": dk, "max_dE": de}
+
+    for precision in ("fp64", "mixed"):
+        b = jk.Batch(plans, nset=nset, precision=precision, mix_threshold=args.mix_threshold)
+        dt = timed_loop(lambda: b.execute(Ds, Js, Ks), steps, warmup, torch)
+        nev, n32 = b.stats()
+        err = errors()
+        res[precision] = {"ms_per_step": dt * 1e3, "molecule_builds_per_s": len(wls) / dt,
+                          "density_builds_per_s": len(wls) * nset / dt, "quartets_per_s": nq / dt,
+                          "fp32_quartets": n32, "fp32_fraction": n32 / max(nev, 1), "vs_oracle": err}
+        log(f"c4 {precision}: {dt * 1e3:.1f} ms per batch ({len(wls) / dt:.0f} molecule builds/s), fp32 fraction "
+            f"{n32 / max(nev, 1):.3f}, vs oracle max|dJ| {err['max_dJ']:.1e} max|dK| {err['max_dK']:.1e} "
+            f"max|dE| {err['max_dE']:.1e}")
+        b.close()
+        # the same molecules one jk_execute each (one warm-up pass, one timed)
+        def one_by_one():
+            for p, D, J, K in zip(plans, Ds, Js, Ks):
+                p.execute(D, J, K, precision=precision, mix_threshold=args.mix_threshold)
+        dts = timed_loop(one_by_one, 1, 1, torch)
+        res[precision]["one_by_one_ms"] = dts * 1e3
+        res[precision]["speedup_vs_one_by_one"] = dts / dt
+        log(f"c4 {precision}: one by one {dts * 1e3:.1f} ms")
+    res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    for p in plans:
+        p.close()
+    return res
+
+
+def bench_dscreen(args, torch, plan, wl, dt_full, steps, warmup):
+    """Incremental build as in a late direct-SCF iteration: the density
+    change dD = 1e-4 * (a fresh seeded density - D) with density screening
+    at --dscreen; its time against the full build, and its error against
+    the same dD built unscreened."""
+    import numpy as np
+    from paper_2507_09772_amd import synth
+    nocc = int(np.rint(np.trace(wl.D[0])))  # D = C C^T with orthonormal C
+    D2 = synth.random_density(wl.mol.nao, nocc, [999, 1], wl.D.shape[0])
+    dD = torch.from_numpy(1e-4 * (D2 - wl.D)).cuda()
+    J = torch.empty_like(dD)
+    K = torch.empty_like(dD)
+    plan.set_density_screening(0.0)
+    plan.execute(dD, J, K)
+    torch.cuda.synchronize()
+    J0, K0 = J.cpu().numpy(), K.cpu().numpy()
+    plan.set_density_screening(args.dscreen)
+    dt = timed_loop(lambda: plan.execute(dD, J, K), steps, warmup, torch)
+    st = plan.stats()
+    plan.set_density_screening(0.0)
+    err_j = float(np.abs(J.cpu().numpy() - J0).max())
+    err_k = float(np.abs(K.cpu().numpy() - K0).max())
+    log(f"c1 incremental (dD ~ 1e-4, dscreen {args.dscreen:g}): {dt * 1e3:.2f} ms/build, "
+        f"{st.nquartets_evaluated} of {st.nquartets} quartets, max|dJ| {err_j:.1e} max|dK| {err_k:.1e} vs unscreened")
+    return {"threshold": args.dscreen, "delta_D": "1e-4 * (seeded density - D)", "ms_per_step": dt * 1e3,
+            "builds_per_s": 1.0 / dt, "speedup_vs_full_build": dt_full / dt,
+            "quartets_evaluated": st.nquartets_evaluated,
+            "max_dJ_vs_unscreened": err_j, "max_dK_vs_unscreened": err_k}
+
+
+def bench_micro(args, torch, jk, synth):
+    """Micro-benchmarks after the paper's appendix B, on the c1 / c2
+    geometries with one uniform shell per atom:
+      * (ss|ss) with 1..8 identical primitives per shell (the same contracted
+        function, so the same quartets): FP64 and FP32 time and their ratio;
+      * (dd|dd) and (ff|ff) with 1..4 densities: time against the number of
+        densities, fitted to integral generation + per-density contraction."""
+    import numpy as np
+    out = {"ssss_nprim": [], "ndm": {}}
+    ref = None
+    for npr in range(1, 9):
+        wl = synth.uniform_shell_workload("c1", 0, npr, 0.2700058226)
+        plan = jk.Plan(wl.mol, wl.cutoff)
+        D = torch.from_numpy(wl.D).cuda()
+        J = torch.empty_like(D)
+        K = torch.empty_like(D)
+        row = {"nprim": npr, "nquartets": plan.stats().nquartets}
+        for prec in ("fp64", "fp32"):
+            row[prec + "_ms"] = 1e3 * timed_loop(lambda: plan.execute(D, J, K, precision=prec), args.steps,
+                                                 args.warmup, torch)
+            if prec == "fp64":
+                Jh = J.cpu().numpy()
+                ref = Jh if ref is None else ref
+                row["max_dJ_vs_nprim1"] = float(np.abs(Jh - ref).max())
+        row["fp32_speedup"] = row["fp64_ms"] / row["fp32_ms"]
+        log(f"(ss|ss) nprim {npr}: fp64 {row['fp64_ms']:.3f} ms  fp32 {row['fp32_ms']:.3f} ms  "
+            f"ratio {row['fp32_speedup']:.2f}  (|dJ| vs nprim 1: {row['max_dJ_vs_nprim1']:.1e})")
+        out["ssss_nprim"].append(row)
+        plan.close()
+    for l, lab in ((2, "dddd"), (3, "ffff")):
+        wl = synth.uniform_shell_workload("c2", l, 1, 1.2700058226, nset=4)
+        plan = jk.Plan(wl.mol, wl.cutoff)
+        ts = []
+        J1 = None
+        for n in range(1, 5):
+            D = torch.from_numpy(np.ascontiguousarray(wl.D[:n])).cuda()
+            J = torch.empty_like(D)
+            K = torch.empty_like(D)
+            dt = timed_loop(lambda: plan.execute(D, J, K), args.steps, args.warmup, torch)
+            ts.append(dt * 1e3)
+            if n == 1:
+                J1 = J[0].cpu().numpy()
+            dj = float(np.abs(J[0].cpu().numpy() - J1).max())
+            log(f"({lab[:2]}|{lab[2:]}) ndm {n}: {dt * 1e3:.2f} ms (|dJ[0]| vs ndm 1: {dj:.1e})")
+        slope, icpt = np.polyfit(np.arange(1, 5), ts, 1)
+        out["ndm"][lab] = {"ms": ts, "integral_ms": float(icpt), "per_density_ms": float(slope),
+                           "nquartets": plan.stats().nquartets}
+        plan.close()
     return out
 
 
@@ -147,162 +387,29 @@ def cpu_baseline(wl, target_s: float):
         # aim the next chunk at the remaining time
         n = int(min(npair - used, max(32, used * (target_s - spent) / max(spent, 1e-3))))
     full_s = spent * npair / used
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / full_s, "unit": "builds/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"eight-fold oracle over {used} random bra shell pairs of {npair} (each with all its "
+            "host_cpus": os.cpu_count(), "host_cpu_model": model,
+            "sample": f"c1 eight-fold oracle over {used} random bra shell pairs of {npair} (each with all its "
                       f"canonical kets), {spent:.1f} s, scaled by {npair}/{used} to one build "
                       f"({full_s:.0f} s per build)"}
 
 
-def bench_batch(args, torch, jk, synth):
-    """Batched builds over the 256-molecule set: one graph replay per step
-    against the same molecules built one jk_execute at a time."""
-    import numpy as np
-    wls = synth.batch_workload()
-    t0 = time.perf_counter()
-    plans = [jk.Plan(w.mol, w.cutoff) for w in wls]
-    t_plan = time.perf_counter() - t0
-    Ds = [torch.from_numpy(w.D).cuda() for w in wls]
-    Js = [torch.empty_like(D) for D in Ds]
-    Ks = [torch.empty_like(D) for D in Ds]
-    nset = Ds[0].shape[0]
-    nq = sum(p.stats().nquartets for p in plans)
-    res = {"config": BATCH_TEXT, "nmol": len(wls), "nset": nset, "plan_seconds": t_plan, "nquartets": nq}
-    log(f"batch: {len(wls)} plans in {t_plan:.1f} s, {nq} quartets")
-    # mixed batches only on request: their FP64 list pass is slow for small
-    # molecules (most quartets are above the threshold)
-    for precision in ("fp64",) + (("mixed",) if args.batch_mixed else ()):
-        b = jk.Batch(plans, nset=nset, precision=precision, mix_threshold=args.mix_threshold)
-        for _ in range(max(args.warmup, 1)):
-            b.execute(Ds, Js, Ks)
-        torch.cuda.synchronize()
-        log(f"batch {precision}: warm")
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            b.execute(Ds, Js, Ks)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        e = [2.0 * float(np.sum(w.D * J.cpu().numpy())) for w, J in zip(wls, Js)]
-        log(f"batch {precision}: {dt * 1e3:.1f} ms per batch; now one jk_execute per molecule")
-        # the same molecules one jk_execute each
-        for p, D, J, K in zip(plans, Ds, Js, Ks):
-            p.execute(D, J, K, precision=precision)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            for p, D, J, K in zip(plans, Ds, Js, Ks):
-                p.execute(D, J, K, precision=precision)
-        torch.cuda.synchronize()
-        dts = (time.perf_counter() - t0) / args.steps
-        e1 = [2.0 * float(np.sum(w.D * J.cpu().numpy())) for w, J in zip(wls, Js)]
-        res[precision] = {"ms_per_step": dt * 1e3, "molecule_builds_per_s": len(wls) / dt,
-                          "density_builds_per_s": len(wls) * nset / dt, "quartets_per_s": nq / dt,
-                          "one_by_one_ms": dts * 1e3, "speedup_vs_one_by_one": dts / dt,
-                          "max_dE_J_vs_one_by_one": float(np.abs(np.subtract(e, e1)).max())}
-        log(f"batch {precision}: {dt * 1e3:.2f} ms/step ({len(wls) / dt:.0f} molecule builds/s), one by one "
-            f"{dts * 1e3:.2f} ms")
-        b.close()
-    return res
-
-
-def bench_dscreen(args, torch, plan, wl, dt_full):
-    """Incremental build as in a late direct-SCF iteration: the density
-    change dD = 1e-4 * (a fresh seeded density - D) with density screening
-    at --dscreen; reports its time against the full build, and its error
-    against the same dD built unscreened."""
-    import numpy as np
-    from paper_2507_09772_amd import synth
-    nocc = int(np.rint(np.trace(wl.D[0])))  # D = C C^T with orthonormal C
-    D2 = synth.random_density(wl.mol.nao, nocc, [999, 1], wl.D.shape[0])
-    dD = torch.from_numpy(1e-4 * (D2 - wl.D)).cuda()
-    J = torch.empty_like(dD)
-    K = torch.empty_like(dD)
-    plan.set_density_screening(0.0)
-    plan.execute(dD, J, K)
-    torch.cuda.synchronize()
-    J0, K0 = J.cpu().numpy(), K.cpu().numpy()
-    plan.set_density_screening(args.dscreen)
-    for _ in range(max(args.warmup, 1)):
-        plan.execute(dD, J, K)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.execute(dD, J, K)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    plan.set_density_screening(0.0)
-    err_j = float(np.abs(J.cpu().numpy() - J0).max())
-    err_k = float(np.abs(K.cpu().numpy() - K0).max())
-    log(f"incremental (dD ~ 1e-4, dscreen {args.dscreen:g}): {dt * 1e3:.2f} ms/build, max|dJ| {err_j:.1e} "
-        f"max|dK| {err_k:.1e} vs unscreened")
-    return {"threshold": args.dscreen, "delta_D": "1e-4 * (seeded density - D)", "ms_per_step": dt * 1e3,
-            "builds_per_s": 1.0 / dt, "speedup_vs_full_build": dt_full / dt,
-            "max_dJ_vs_unscreened": err_j, "max_dK_vs_unscreened": err_k}
-
-
-def bench_micro(args, torch, jk, synth):
-    """Micro-benchmarks after the paper's appendix B, on the c1 / c2
-    geometries with one uniform shell per atom:
-      * (ss|ss) with 1..8 identical primitives per shell (the same contracted
-        function, so the same quartets): FP64 and FP32 time and their ratio;
-      * (dd|dd) and (ff|ff) with 1..4 densities: time against the number of
-        densities, fitted to integral generation + per-density contraction."""
-    import numpy as np
-    out = {"ssss_nprim": [], "ndm": {}}
-    ref = None
-    for npr in range(1, 9):
-        wl = synth.uniform_shell_workload("c1", 0, npr, 0.2700058226)
-        plan = jk.Plan(wl.mol, wl.cutoff)
-        D = torch.from_numpy(wl.D).cuda()
-        J = torch.empty_like(D)
-        K = torch.empty_like(D)
-        row = {"nprim": npr, "nquartets": plan.stats().nquartets}
-        for prec in ("fp64", "fp32"):
-            dt, _ = timed_steps(plan, D, J, K, prec, args.steps, args.warmup, torch)
-            row[prec + "_ms"] = dt * 1e3
-            if prec == "fp64":
-                Jh = J.cpu().numpy()
-                ref = Jh if ref is None else ref
-                row["max_dJ_vs_nprim1"] = float(np.abs(Jh - ref).max())
-        row["fp32_speedup"] = row["fp64_ms"] / row["fp32_ms"]
-        log(f"(ss|ss) nprim {npr}: fp64 {row['fp64_ms']:.3f} ms  fp32 {row['fp32_ms']:.3f} ms  "
-            f"ratio {row['fp32_speedup']:.2f}  (|dJ| vs nprim 1: {row['max_dJ_vs_nprim1']:.1e})")
-        out["ssss_nprim"].append(row)
-        plan.close()
-    for l, lab in ((2, "dddd"), (3, "ffff")):
-        wl = synth.uniform_shell_workload("c2", l, 1, 1.2700058226, nset=4)
-        plan = jk.Plan(wl.mol, wl.cutoff)
-        ts = []
-        J1 = None
-        for n in range(1, 5):
-            D = torch.from_numpy(np.ascontiguousarray(wl.D[:n])).cuda()
-            J = torch.empty_like(D)
-            K = torch.empty_like(D)
-            dt, _ = timed_steps(plan, D, J, K, "fp64", args.steps, args.warmup, torch)
-            ts.append(dt * 1e3)
-            if n == 1:
-                J1 = J[0].cpu().numpy()
-            dj = float(np.abs(J[0].cpu().numpy() - J1).max())
-            log(f"({lab[:2]}|{lab[2:]}) ndm {n}: {dt * 1e3:.2f} ms (|dJ[0]| vs ndm 1: {dj:.1e})")
-        slope, icpt = np.polyfit(np.arange(1, 5), ts, 1)
-        out["ndm"][lab] = {"ms": ts, "integral_ms": float(icpt), "per_density_ms": float(slope),
-                           "nquartets": plan.stats().nquartets}
-        plan.close()
-    return out
-
-
 def main():
-    ap = argparse.ArgumentParser(description=__doc__)
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=5, help="timed steps of the headline (c1) builds")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c1", choices=sorted(WORKLOAD_TEXT) + ["c4"],
-                    help="c4: only the 256-molecule batched builds")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--configs", default="c1,c2,c4", help="comma list of c1, c2, c4 (c1 is always run)")
+    ap.add_argument("--steps-other", type=int, default=5, help="most timed steps of c2 and c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 256-molecule batched builds")
     ap.add_argument("--no-dscreen", action="store_true", help="skip the incremental (density-screened) build")
     ap.add_argument("--micro", action="store_true", help="only the appendix-B style micro-benchmarks")
-    ap.add_argument("--batch-mixed", action="store_true", help="also time mixed-precision batches")
     ap.add_argument("--dscreen", type=float, default=1e-10, help="density screening threshold")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mix-threshold", type=float, default=1e-4)
@@ -315,7 +422,6 @@ def main():
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2507_09772_amd import jk, synth
@@ -334,82 +440,38 @@ def main():
     if args.micro:
         print(json.dumps({"micro": bench_micro(args, torch, jk, synth)}), flush=True)
         return
-    if args.workload == "c4":
-        res = bench_batch(args, torch, jk, synth)
-        r64 = res["fp64"]
-        out = {"metric": METRIC, "value": r64["molecule_builds_per_s"], "unit": "molecule builds/s", "n_gpus": 1,
-               "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
-               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-               "data": "synthetic (seeded water clusters, random orthonormal C)",
-               "config": {"workload": f"c4: {BATCH_TEXT}", "precision": "fp64"}, "batch": res,
-               "roofline": None, "cpu_baseline": None}
-        print(json.dumps(out), flush=True)
-        return
-    wl = synth.workload(args.workload)
-    log(f"workload {args.workload}: {wl.mol.nshell} shells, {wl.mol.nao} AOs")
-    t0 = time.perf_counter()
-    plan = jk.Plan(wl.mol, wl.cutoff)
-    st = plan.stats()
-    log(f"plan: {time.perf_counter() - t0:.2f} s, {st.nquartets} quartets, {st.nprim_quartets} primitive "
-        f"quartets, {st.nclasses} classes")
-    D = torch.from_numpy(wl.D).cuda()
-    J = torch.empty_like(D)
-    K = torch.empty_like(D)
+    which = [c.strip() for c in args.configs.split(",") if c.strip()]
+    so, wo = max(1, min(args.steps, args.steps_other)), max(1, min(args.warmup, 2))
 
-    dt64, tim64 = timed_steps(plan, D, J, K, "fp64", args.steps, args.warmup, torch, profile=True)
-    log(f"fp64: {dt64 * 1e3:.2f} ms/build")
-    D_h = wl.D
-    J64, K64 = J.cpu().numpy(), K.cpu().numpy()
-    ej64 = 2.0 * float(np.sum(D_h * J64))
-    ek64 = float(np.sum(D_h * K64))
-
-    # dominant kernel: group the per-launch timings by kernel instantiation
-    # (class, family, precision, kind), as the profiler groups by name
-    kern = kernel_groups(tim64)
-    dom_name, dom = max(kern.items(), key=lambda kv: kv[1]["ms"])
-    avg_ms = dom["ms"] / dom["launches"]
-    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-    traffic, traffic_src = hbm_traffic(dom_name) if args.workload == "c1" else (None, "counters taken for c1 only")
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VECTOR, "traffic": traffic, "traffic_source": traffic_src,
-                "kernel": dom_name,
-                "avg_launch_ms": avg_ms, "launches_per_build": dom["launches"] / args.steps,
-                "model_flops_per_launch": dom["flops"] / dom["launches"],
-                "share_of_build": dom["ms"] / args.steps / (dt64 * 1e3)}
-    whole = st.model_flops / dt64 / 1e12
-    for name, k in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])[:args.top]:
-        log(f"  {name:44s} {k['ms'] / args.steps:8.3f} ms/build  {k['launches'] / args.steps:4.0f} launches  "
-            f"{k['flops'] / (k['ms'] * 1e-3) / 1e12 if k['ms'] > 0 else 0:6.2f} TF/s")
-
-    out = {"metric": METRIC, "value": 1.0 / dt64, "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": dt64 * 1e3, "higher_is_better": True, "scaling": "weak",
+    c1 = bench_molecule("c1", args, torch, jk, synth, args.steps, args.warmup)
+    r64 = c1["fp64"]
+    out = {"metric": METRIC, "value": r64["builds_per_s"], "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded water lattice, random orthonormal C)",
-           "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "nset": 1,
-                      "precision": "fp64", "cutoff": wl.cutoff},
-           "quartets_per_s": st.nquartets / dt64, "prim_quartets_per_s": st.nprim_quartets / dt64,
-           "nquartets": st.nquartets, "model_tflops": whole, "model_frac_fp64_peak": whole / PEAK_FP64_VECTOR,
-           "E_J": ej64, "E_K": ek64, "roofline": roofline}
-
-    if not args.no_mixed:
-        dtm, timm = timed_steps(plan, D, J, K, "mixed", args.steps, args.warmup, torch, profile=True)
-        Jm, Km = J.cpu().numpy(), K.cpu().numpy()
-        ejm, ekm = 2.0 * float(np.sum(D_h * Jm)), float(np.sum(D_h * Km))
-        f32 = sum(t.ms for t in timm if t.precision == jk.JK_FP32)
-        f64 = sum(t.ms for t in timm if t.precision == jk.JK_FP64)
-        log(f"mixed: {dtm * 1e3:.2f} ms/build (fp64 kernels {f64 / args.steps:.2f} ms, fp32 kernels "
-            f"{f32 / args.steps:.2f} ms), dE_J {ejm - ej64:.2e} dE_K {ekm - ek64:.2e}")
-        out["mixed"] = {"builds_per_s": 1.0 / dtm, "quartets_per_s": st.nquartets / dtm, "ms_per_step": dtm * 1e3,
-                        "speedup_vs_fp64": dt64 / dtm, "dE_J_vs_fp64_gpu": ejm - ej64, "dE_K_vs_fp64_gpu": ekm - ek64,
-                        "max_dJ_vs_fp64_gpu": float(np.abs(Jm - J64).max()),
-                        "max_dK_vs_fp64_gpu": float(np.abs(Km - K64).max()),
-                        "threshold": args.mix_threshold}
-    if not args.no_dscreen:
-        out["density_screening"] = bench_dscreen(args, torch, plan, wl, dt64)
-    if not args.no_batch:
-        out["batch"] = bench_batch(args, torch, jk, synth)
+           "config": {"workload": c1["workload"], "nset": 1, "precision": "fp64", "cutoff": 1e-13},
+           "quartets_per_s": r64["quartets_per_s"], "prim_quartets_per_s": r64["prim_quartets_per_s"],
+           "nquartets": c1["nquartets"], "model_tflops": r64["model_tflops"],
+           "model_frac_fp64_peak": r64["frac_of_vector_roofline"], "roofline": r64["roofline"],
+           "configs": {"c1": c1}}
+    if "c2" in which:
+        out["configs"]["c2"] = bench_molecule("c2", args, torch, jk, synth, so, wo)
+    # config 3: the mixed split on the c1 and c2 molecules
+    c3 = {}
+    for n in ("c1", "c2"):
+        if n in out["configs"]:
+            m = out["configs"][n]["mixed"]
+            c3[n] = {"fp32_fraction": m["fp32_fraction"], "speedup_vs_fp64": m["speedup_vs_fp64"],
+                     "builds_per_s": m["builds_per_s"], "quartets_per_s": m["quartets_per_s"],
+                     "frac_of_vector_roofline": m["frac_of_vector_roofline"],
+                     "max_dJ": m["vs_oracle"]["max_dJ"], "max_dK": m["vs_oracle"]["max_dK"],
+                     "dE_J": m["vs_oracle"]["dE_J"], "dE_K": m["vs_oracle"]["dE_K"],
+                     "threshold": args.mix_threshold}
+    out["configs"]["c3"] = c3
+    if "c4" in which:
+        out["configs"]["c4"] = bench_batch(args, torch, jk, synth, so, wo)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(synth.workload("c1"), args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

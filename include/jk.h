@@ -41,7 +41,8 @@ extern "C" {
 enum {
     JK_OK = 0,
     JK_EINVAL = -1,        /* bad argument: sizes, ranges, non-finite values */
-    JK_EUNSUPPORTED = -2,  /* valid but not implemented (l > JK_LMAX) */
+    JK_EUNSUPPORTED = -2,  /* valid but not built: a shell with l above the
+                              built maximum (JK_LMAX_BUILT), too many quartets */
     JK_ENOMEM = -3,        /* device or host allocation failed */
     JK_EDEVICE = -4        /* a HIP call failed */
 };
@@ -49,11 +50,10 @@ enum {
 /* Arithmetic of the integral evaluation (Table 1's DataType). */
 enum {
     JK_FP64 = 0,   /* every quartet in FP64 */
-    JK_MIXED = 1,  /* quartets whose bound Q_IJ Q_KL max|D_block| < mix_threshold in
-                      FP32, the rest in FP64; accumulation always FP64.  On gfx950
-                      only the one-root classes ((ss|ss), (ps|ss)) are split: single
-                      precision gains nothing elsewhere, so the other classes run
-                      in FP64 throughout */
+    JK_MIXED = 1,  /* every quartet whose bound Q_IJ Q_KL max|D_block| (FP64, the
+                      largest |D| over the six blocks the quartet touches and over
+                      the densities) is below mix_threshold runs in FP32, the rest
+                      in FP64, in every angular class; accumulation always FP64 */
     JK_FP32 = 2    /* every quartet in FP32, FP64 accumulation */
 };
 
@@ -61,10 +61,14 @@ enum {
 enum {
     JK_DO_J = 1,
     JK_DO_K = 2,
-    JK_ACCUMULATE = 4  /* add into J/K instead of overwriting them */
+    JK_ACCUMULATE = 4,     /* add into J/K instead of overwriting them */
+    JK_CHECK_SYMMETRY = 8  /* check on the device that every D is finite and
+                              symmetric (max|D - D^T| <= 1e-12 max|D|) before the
+                              build; JK_EINVAL otherwise.  Synchronises the stream */
 };
 
-#define JK_LMAX 4       /* highest shell angular momentum (g) */
+#define JK_LMAX 4       /* highest angular momentum the basis format admits (g) */
+#define JK_LMAX_BUILT 3 /* highest one with built kernels (f); l = 4 -> JK_EUNSUPPORTED */
 #define JK_MAXPRIM 16   /* most primitives per shell */
 
 /* Basis description, host memory, owned by the caller, read only during the
@@ -73,7 +77,8 @@ typedef struct {
     int32_t nshell;
     int32_t natom;
     int32_t spherical;      /* 0 Cartesian, 1 real solid harmonics */
-    const int32_t *l;       /* [nshell] 0..JK_LMAX */
+    const int32_t *l;       /* [nshell] 0..JK_LMAX (l > JK_LMAX: JK_EINVAL;
+                               JK_LMAX_BUILT < l <= JK_LMAX: JK_EUNSUPPORTED) */
     const int32_t *nprim;   /* [nshell] 1..JK_MAXPRIM */
     const int32_t *atom;    /* [nshell] 0..natom-1 */
     const double *exps;     /* [sum nprim] > 0, grouped by shell in shell order */
@@ -88,12 +93,14 @@ typedef struct jk_batch jk_batch;
 typedef struct {
     int64_t nquartets;          /* significant unique shell quartets */
     int64_t nprim_quartets;     /* primitive quartets inside them */
-    int64_t nquartets_fp32;     /* quartets run in FP32 by the last JK_MIXED execute
-                                   (split classes only) */
+    int64_t nquartets_fp32;     /* quartets the last build ran in FP32 (JK_MIXED: those
+                                   below the threshold; JK_FP32: all evaluated) */
     int32_t nclasses;           /* (bra pair type, ket pair type) launches */
     int32_t npairs;             /* shell pairs kept after screening */
     double setup_ms;            /* jk_plan_create wall time */
     double model_flops;         /* algorithmic FLOPs of one build with nset = 1 */
+    int64_t nquartets_evaluated; /* quartets the last build evaluated (nquartets less
+                                    those dropped by density screening) */
 } jk_stats;
 
 /*
@@ -126,11 +133,14 @@ int jk_plan_schwarz(const jk_plan *plan, double *Q_host);
  * erf(omega r)/r, < 0 the short-range erfc(|omega| r)/r; the screening uses
  * the Coulomb Schwarz factors in every case (they bound both parts); non-
  * finite omega -> JK_EINVAL.  Asynchronous on
- * stream; D/J/K must stay valid until the stream reaches this point.
- * nset >= 1.
+ * stream (unless JK_CHECK_SYMMETRY); D/J/K must stay valid until the stream
+ * reaches this point.  nset >= 1.  Scratch (Cartesian J', K', density, the
+ * block maxima) is allocated by the plan at the first call that needs it
+ * and reused; calls on one plan must be ordered.
  */
 int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int32_t precision,
                double mix_threshold, double omega, double *J, double *K, void *stream);
+
 
 /*
  * Density screening for direct SCF (Section 2: the screening of the J and K
@@ -138,7 +148,7 @@ int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int3
  * later jk_execute calls on this plan drop every quartet with
  *   Q_IJ Q_KL max(Dm_IJ, Dm_KL, Dm_IK, Dm_IL, Dm_JK, Dm_JL) < threshold,
  * Dm_XY the largest |D| over the densities and the Cartesian components of
- * block (X, Y) (single precision), so each dropped contribution to any J or
+ * block (X, Y) (double precision), so each dropped contribution to any J or
  * K element is below the threshold.  Passing the density change Delta D with
  * JK_ACCUMULATE builds the incremental J += Delta J, K += Delta K.
  * threshold = 0 turns it off (the default).  JK_EINVAL for a NULL plan or a
@@ -164,15 +174,19 @@ int jk_build(const jk_basis *basis, const double *D, int32_t nset, double cutoff
  *   D[m], J[m], K[m]: device FP64 [nset][nao_m][nao_m] of molecule m; D[m]
  *                symmetric.  Pointers may change between calls (a small
  *                host-to-device update on the stream precedes the replay).
- * Scratch (Cartesian D, J', K', lists) is owned by the batch and shared by
- * its calls: calls on one batch must be ordered (same stream, or the caller
- * synchronises); concurrent calls race.  Errors: JK_EINVAL for NULL or
- * mismatched arguments, JK_ENOMEM, JK_EDEVICE.
+ * Scratch (Cartesian D, J', K', block maxima, counters) is owned by the
+ * batch and shared by its calls: calls on one batch must be ordered (same
+ * stream, or the caller synchronises); concurrent calls race.  Errors:
+ * JK_EINVAL for NULL or mismatched arguments (checked before anything
+ * changes), JK_ENOMEM, JK_EDEVICE.
+ * jk_batch_stats: quartets the last execute evaluated over all molecules,
+ * and how many of them in FP32 (mixed precision); synchronises the device.
  */
 int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset, int32_t precision,
                     double mix_threshold, jk_batch **out);
 int jk_batch_execute(jk_batch *batch, const double *const *D, double *const *J, double *const *K,
                      void *stream);
+int jk_batch_stats(const jk_batch *batch, int64_t *nquartets, int64_t *nquartets_fp32);
 void jk_batch_destroy(jk_batch *batch);
 
 /*
@@ -209,9 +223,10 @@ typedef struct {
     int32_t precision;          /* JK_FP64 or JK_FP32 */
     int32_t launches;           /* launches summed into ms (one per build) */
     int32_t family;             /* kernel family (1, 2) */
-    int32_t kind;               /* 0 tiles, 1 row mode (long bras, 256-lane workgroups), 2 list (FP64
-                                   part of the mixed split), 3 row mode (short bras, 64-lane) */
-    int64_t nquartets;          /* quartets processed, summed over the launches (0 for kind 2) */
+    int32_t kind;               /* 0 tiles, 1 row mode (long bras, 256-lane workgroups), 3 row mode
+                                   (short bras, 64-lane workgroups); 2 is not used */
+    int64_t nquartets;          /* quartets evaluated, summed over the launches (after the mixed
+                                   split and density screening) */
     double model_flops;         /* their algorithmic FLOPs (nset = 1), summed likewise */
     double ms;                  /* summed kernel time */
 } jk_class_timing;
@@ -222,26 +237,36 @@ int jk_plan_timings(const jk_plan *plan, jk_class_timing *out, int32_t cap, int3
 /*
  * Kernel tuning table (the per-device heuristics database of Section 3).
  * Every canonical angular class (li >= lj, lk >= ll, (lk,ll) <= (li,lj))
- * has up to two kernel families: 1 = one lane per quartet with the integral
- * block in registers, 2 = a lane group per quartet with 2-D integrals in
- * LDS.  jk_tune_set picks the family for one class and precision (JK_FP64
- * or JK_FP32; family 0 restores the built-in default); plans read the table
- * when they are created.  jk_tune_set_row controls row mode for one class
- * and precision (0 default = 1; 1 bras with long ket prefixes; 2 off; 3 every
- * bra, the short ones in 64-lane workgroups): in row mode a workgroup walks
- * (a chunk of) one bra's ket prefix and keeps the bra's K rows in LDS, so
- * most J/K updates stay out of global atomics; batched builds run every bra
- * of a class as 64-lane row tasks unless its setting is 2.  At load time
- * the library reads tune_gfx950.txt next to itself (or the file named by
+ * has up to three kernel families: 1 = one lane per quartet with the
+ * integral block in registers; 2 = a lane group per quartet with the 2-D
+ * integrals of all roots in LDS; 3 = a lane per Cartesian component of the
+ * bra's first shell, its elements in registers and only the vertical
+ * recurrence tables in LDS (row mode only: bras with short ket prefixes run
+ * as tiles of family 2, or 1 where 2 is not built).  jk_tune_set picks the
+ * family for one class and precision (JK_FP64 or JK_FP32; family 0
+ * restores the built-in default); plans read the table when they are
+ * created.  jk_tune_set_row controls row mode for one class and precision
+ * (0 default = 1; 1 bras with long ket prefixes; 2 off; 3 every bra, the
+ * short ones in 64-lane workgroups): in row mode a workgroup walks (a chunk
+ * of) one bra's ket prefix and keeps the bra's K rows in LDS, so most J/K
+ * updates stay out of global atomics; batched builds run every bra of a
+ * class as 64-lane row tasks unless its setting is 2.  At load time the
+ * library reads tune_gfx950.txt next to itself (or the file named by
  * JK_TUNE_DB): one "li lj lk ll precision family [row]" line per entry,
- * '#' comments.
+ * "shape ..." lines (jk_tune_set_shape), '#' comments.
  * jk_tune_get reports the family a new plan would use and a bit mask of
- * the built families (1: family 1, 2: family 2).
+ * the built families (1: family 1, 2: family 2, 4: family 3).
  */
 int jk_tune_set(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family);
 int jk_tune_set_row(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t row);
 int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t *family,
                 int32_t *available);
+/* Task shape of one class (the fragmentation of Section 3.2), read by plans
+ * created afterwards: bras with at least min_kets kets run in row mode
+ * (default 192) and one row task covers at most chunk kets of a bra (default:
+ * 2048 for family 1, 256 wave steps for families 2 and 3); 0 restores a
+ * default.  Table lines "shape li lj lk ll min_kets chunk". */
+int jk_tune_set_shape(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t min_kets, int32_t chunk);
 int jk_tune_load(const char *path);
 
 const char *jk_last_error(void);

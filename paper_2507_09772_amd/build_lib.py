@@ -30,7 +30,30 @@ def _run(cmd):
     return r
 
 
-def build(jobs: int | None = None, extra=(), verbose=False) -> str:
+# sources a kernel unit (kern_bra.hip) depends on; the other units depend on
+# every source
+_KERN_DEPS = ("kern_bra.hip", "jk_registry.h", "jk_device.h", "jk_common.h", "tables/jk_tables_meta.h",
+              "tables/jk_tables_mom_meta.h")
+
+
+def _stale(obj: str, kernel_unit: bool) -> bool:
+    """True when obj is older than a source it depends on (incremental
+    builds during development; build() without incremental compiles all)."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    if kernel_unit:
+        deps = [os.path.join(CSRC, d) for d in _KERN_DEPS]
+    else:
+        deps = [os.path.join(d, f) for d, _, fs in os.walk(CSRC) for f in fs]
+        deps.append(os.path.join(ROOT, "include", "jk.h"))
+    deps.append(__file__)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(jobs: int | None = None, extra=(), verbose=False, incremental=False) -> str:
+    """Compile every unit (incremental: only units older than a source) and
+    link libjk.so."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     jobs = jobs or min(16, os.cpu_count() or 4)
@@ -45,6 +68,8 @@ def build(jobs: int | None = None, extra=(), verbose=False) -> str:
         for name, src, defs in units:
             obj = os.path.join(BUILD, name + ".o")
             objs.append(obj)
+            if incremental and not _stale(obj, name.startswith("kern")):
+                continue
             cmd = [hipcc, *FLAGS, *extra, *defs, "-c", src, "-o", obj]
             futs[ex.submit(_run, cmd)] = name
         for f in cf.as_completed(futs):
@@ -58,4 +83,4 @@ def build(jobs: int | None = None, extra=(), verbose=False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

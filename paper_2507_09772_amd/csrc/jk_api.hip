@@ -36,9 +36,15 @@ static int32_t g_tune[NCLS][2];
 // Row mode per (class, precision): 0 default (allowed), 1 allowed, 2 off.
 static int32_t g_row[NCLS][2];
 static void ensure_tuning();
+static int launch_counts(const jk_plan *P, std::vector<int64_t> *out);
 
-// Bras with at least this many kets run in row mode (one workgroup each).
+// Task shape per class (host side; 0 = default): bras with at least
+// min_kets kets run in row mode (the default 192), and a row task covers at
+// most chunk kets of one bra (by default row_chunk of the family; a set
+// value applies to the row tasks of every family).
 static const int ROW_MIN_KETS = 192;
+static int32_t g_minkets[NCLS];
+static int32_t g_chunk[NCLS];
 
 // ---------------------------------------------------------------------------
 // errors
@@ -174,10 +180,24 @@ __global__ void k_finalize(AoMaps m, const double *X, double *out, int nao, int 
 }
 
 // dmax[I][J] = max_s max_{a in I, b in J} |Dc[s][a][b]|
-__global__ void k_dmax(const double *Dc, const int32_t *aoc, const int32_t *l, int ns, int naoc, int nset, float *dmax) {
+__global__ void k_dmax(const double *Dc, const int32_t *aoc, const int32_t *l, int ns, int naoc, int nset, double *dmax) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ns * ns) return;
     dmax[t] = dmax_elem(Dc, aoc, l, ns, naoc, nset, t);
+}
+
+// dmax[ns * ns] = the largest entry of the table (one workgroup).
+__global__ void __launch_bounds__(256) k_dmax_all(double *dmax, int ns) {
+    __shared__ double part[256];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < ns * ns; t += 256) m = fmax(m, dmax[t]);
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dmax[ns * ns] = part[0];
 }
 
 template <int N, typename R>
@@ -461,11 +481,11 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
             c.npb = P->hpairs[ptype_first[bt]].npp;
             c.npk = P->hpairs[ptype_first[kt]].npp;
             const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
-            const bool avail[2] = {ce.tiles[0][0] != nullptr, ce.tiles[1][0] != nullptr};
+            const bool avail[3] = {ce.tiles[0][0] != nullptr, ce.tiles[1][0] != nullptr, ce.row[2][0] != nullptr};
             if (!avail[0] && !avail[1]) return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) not built", c.li, c.lj, c.lk, c.ll);
             for (int pr = 0; pr < 2; ++pr) {
                 int f = g_tune[class_id(c.li, c.lj, c.lk, c.ll)][pr];
-                if (f < 1 || f > 2 || !avail[f - 1]) f = default_family(c.li, c.lj, c.lk, c.ll);
+                if (f < 1 || f > 3 || !avail[f - 1]) f = default_family(c.li, c.lj, c.lk, c.ll);
                 if (!avail[f - 1]) f = 3 - f;
                 c.fam[pr] = f;
                 c.row_ok[pr] = g_row[class_id(c.li, c.lj, c.lk, c.ll)][pr] != 2;
@@ -507,7 +527,6 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 if (avail[f] && (rc = P->put(&c.d_tile[f], to[f]))) return rc;
             }
             c.d_ket = d_sorted[kt];
-            c.list_off = nq_tot;
             // row mode split: bras with a long ket prefix get a workgroup each
             {
                 const int tK = ptype_key[kt] / ntype, tL = ptype_key[kt] % ntype;
@@ -519,7 +538,9 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 std::vector<int32_t> rows, sb, scn, sto[2];
                 int64_t st[2] = {0, 0};
                 for (size_t i = 0; i < bl.size(); ++i) {
-                    if (cn[i] >= ROW_MIN_KETS) {
+                    const int minkets = g_minkets[class_id(c.li, c.lj, c.lk, c.ll)] > 0
+                                            ? g_minkets[class_id(c.li, c.lj, c.lk, c.ll)] : ROW_MIN_KETS;
+                    if (cn[i] >= minkets) {
                         rows.push_back((int32_t)i);
                         c.nq_row += cn[i];
                         continue;
@@ -538,12 +559,13 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 }
                 c.nrow = (int)rows.size();
                 c.nsbra = (int)sb.size();
-                if (c.nrow > 0 && (ce.row[0][0] || ce.row[1][0])) {
+                if (c.nrow > 0 && (ce.row[0][0] || ce.row[1][0] || ce.row[2][0])) {
                     // row tasks: (list position, first ket, end ket), each long
                     // bra cut into near-equal chunks of at most row_chunk kets
-                    for (int f = 0; f < 2; ++f) {
+                    for (int f = 0; f < 3; ++f) {
                         if (!ce.row[f][0]) continue;
-                        const int ch = row_chunk(f + 1, c.li, c.lj, c.lk, c.ll);
+                        const int gch = g_chunk[class_id(c.li, c.lj, c.lk, c.ll)];
+                        const int ch = gch > 0 ? gch : row_chunk(f + 1, c.li, c.lj, c.lk, c.ll);
                         std::vector<int32_t> tasks;
                         for (int32_t i : rows) {
                             const int64_t n = cn[i], nch = (n + ch - 1) / ch, len = (n + nch - 1) / nch;
@@ -569,7 +591,8 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                     c.nq_row = 0;
                 }
                 c.nsrow = (int)(c.h_srowt.size() / 3);
-                if (c.nsrow > 0 && (ce.srow[0][0] || ce.srow[1][0]) && (rc = P->put(&c.d_srowt, c.h_srowt))) return rc;
+                if (c.nsrow > 0 && (ce.srow[0][0] || ce.srow[1][0] || ce.srow[2][0]) && (rc = P->put(&c.d_srowt, c.h_srowt)))
+                    return rc;
             }
             nq_tot += c.nq;
             npq_tot += c.npq;
@@ -617,18 +640,17 @@ extern "C" int jk_plan_stats(const jk_plan *P, jk_stats *st) {
     if (!P || !st) return fail(JK_EINVAL, "NULL argument");
     *st = P->stats;
     st->nquartets_fp32 = 0;
-    if (P->last_mixed && P->d_list_cnt && !P->cls.empty()) {
-        std::vector<int32_t> cnt(P->cls.size());
+    st->nquartets_evaluated = 0;
+    if (P->last_nsel && !P->cls.empty()) {
+        // the counters of the last build: [class][precision][kind]
+        std::vector<int64_t> cnt;
         HIPCHK(hipDeviceSynchronize());
-        HIPCHK(hipMemcpy(cnt.data(), P->d_list_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost));
-        // split classes only: their quartets minus those diverted to the
-        // FP64 list (the other classes run in FP64 throughout)
-        int64_t n32 = 0;
-        for (size_t ci = 0; ci < P->cls.size(); ++ci) {
-            const ClassTask &c = P->cls[ci];
-            if (mixed_split_class(c.li, c.lj, c.lk, c.ll)) n32 += c.nq - cnt[ci];
+        const int rc = launch_counts(P, &cnt);
+        if (rc) return rc;
+        for (size_t k = 0; k < cnt.size(); ++k) {
+            st->nquartets_evaluated += cnt[k];
+            if ((k / 4) % 2 == 1) st->nquartets_fp32 += cnt[k];
         }
-        st->nquartets_fp32 = n32;
     }
     return 0;
 }
@@ -644,9 +666,10 @@ static bool valid_class(int li, int lj, int lk, int ll) {
 static int tune_set_impl(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t family) {
     if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
     if (precision != JK_FP64 && precision != JK_FP32) return fail(JK_EINVAL, "precision must be JK_FP64 or JK_FP32");
-    if (family < 0 || family > 2) return fail(JK_EINVAL, "family must be 0, 1 or 2");
+    if (family < 0 || family > 3) return fail(JK_EINVAL, "family must be 0, 1, 2 or 3");
     const ClassEntry &e = g_classes[class_id(li, lj, lk, ll)];
-    if (family && !e.tiles[family - 1][0]) return fail(JK_EUNSUPPORTED, "family %d is not built for (%d%d|%d%d)", family, li, lj, lk, ll);
+    const bool built = family == 3 ? e.row[2][0] != nullptr : family ? e.tiles[family - 1][0] != nullptr : true;
+    if (!built) return fail(JK_EUNSUPPORTED, "family %d is not built for (%d%d|%d%d)", family, li, lj, lk, ll);
     g_tune[class_id(li, lj, lk, ll)][precision == JK_FP32 ? 1 : 0] = family;
     return 0;
 }
@@ -670,6 +693,20 @@ extern "C" int jk_tune_set_row(int32_t li, int32_t lj, int32_t lk, int32_t ll, i
     return tune_set_row_impl(li, lj, lk, ll, precision, row);
 }
 
+static int tune_set_shape_impl(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t min_kets, int32_t chunk) {
+    if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
+    if (min_kets < 0 || min_kets > (1 << 24) || chunk < 0 || chunk > (1 << 24))
+        return fail(JK_EINVAL, "min_kets and chunk must be in 0..2^24 (0: default)");
+    g_minkets[class_id(li, lj, lk, ll)] = min_kets;
+    g_chunk[class_id(li, lj, lk, ll)] = chunk;
+    return 0;
+}
+
+extern "C" int jk_tune_set_shape(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t min_kets, int32_t chunk) {
+    ensure_tuning();
+    return tune_set_shape_impl(li, lj, lk, ll, min_kets, chunk);
+}
+
 extern "C" int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t *family,
                            int32_t *available) {
     ensure_tuning();
@@ -678,7 +715,7 @@ extern "C" int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32
     const ClassEntry &e = g_classes[class_id(li, lj, lk, ll)];
     const int f = g_tune[class_id(li, lj, lk, ll)][precision == JK_FP32 ? 1 : 0];
     if (family) *family = f ? f : default_family(li, lj, lk, ll);
-    if (available) *available = (e.tiles[0][0] ? 1 : 0) | (e.tiles[1][0] ? 2 : 0);
+    if (available) *available = (e.tiles[0][0] ? 1 : 0) | (e.tiles[1][0] ? 2 : 0) | (e.row[2][0] ? 4 : 0);
     return 0;
 }
 
@@ -692,6 +729,17 @@ static int tune_load_impl(const char *path) {
         ++lineno;
         if (line[0] == '#' || line[0] == '\n') continue;
         int li, lj, lk, ll, pr, fam, row = 0;
+        if (strncmp(line, "shape", 5) == 0) {
+            int mk = 0, ch = 0;
+            if (sscanf(line + 5, "%d %d %d %d %d %d", &li, &lj, &lk, &ll, &mk, &ch) != 6) {
+                fclose(f);
+                return fail(JK_EINVAL, "%s:%d: expected 'shape li lj lk ll min_kets chunk'", path, lineno);
+            }
+            const int rc = tune_set_shape_impl(li, lj, lk, ll, mk, ch);
+            if (rc) { fclose(f); return rc; }
+            ++n;
+            continue;
+        }
         const int got = sscanf(line, "%d %d %d %d %d %d %d", &li, &lj, &lk, &ll, &pr, &fam, &row);
         if (got != 6 && got != 7) {
             fclose(f);
@@ -747,41 +795,69 @@ extern "C" int jk_plan_schwarz(const jk_plan *P, double *Q) {
 
 static int grid_for(int64_t n, int block) { return (int)std::min<int64_t>((n + block - 1) / block, 65536); }
 
-static int ensure_scratch(jk_plan *P, int nset, bool need_dc) {
+static void drop_alloc(jk_plan *P, void *p) {
+    if (!p) return;
+    (void)hipFree(p);
+    P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), p));
+}
+
+// The plan's own scratch, grown on demand (jk_execute).
+static int ensure_scratch(jk_plan *P, int nset, Scratch *sc) {
     const size_t m = (size_t)P->naoc * P->naoc;
+    int rc;
     if (P->scratch_nset < nset) {
-        if (P->d_Jc) { (void)hipFree(P->d_Jc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Jc)); }
-        if (P->d_Kc) { (void)hipFree(P->d_Kc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Kc)); }
-        if (P->d_jp) { (void)hipFree(P->d_jp); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_jp)); }
+        drop_alloc(P, P->d_Jc);
+        drop_alloc(P, P->d_Kc);
+        drop_alloc(P, P->d_jp);
         P->d_Jc = P->d_Kc = P->d_jp = nullptr;
         P->scratch_nset = 0;
-        int rc;
         if ((rc = P->alloc(&P->d_Jc, m * nset)) || (rc = P->alloc(&P->d_Kc, m * nset)) ||
             (rc = P->alloc(&P->d_jp, (size_t)P->njp * nset)))
             return rc;
         P->scratch_nset = nset;
     }
-    if (need_dc && P->dc_nset < nset) {
-        if (P->d_Dc) { (void)hipFree(P->d_Dc); P->allocs.erase(std::find(P->allocs.begin(), P->allocs.end(), (void *)P->d_Dc)); }
+    if (P->sph && P->dc_nset < nset) {
+        drop_alloc(P, P->d_Dc);
         P->d_Dc = nullptr;
         P->dc_nset = 0;
-        int rc;
         if ((rc = P->alloc(&P->d_Dc, m * nset))) return rc;
         P->dc_nset = nset;
     }
-    if (!P->d_dmax) {
-        int rc;
-        if ((rc = P->alloc(&P->d_dmax, (size_t)P->ns * P->ns))) return rc;
+    if (!P->d_dmax && (rc = P->alloc(&P->d_dmax, scratch_sizes(P, 1).dmax))) return rc;
+    if (!P->d_nsel && (rc = P->alloc(&P->d_nsel, scratch_sizes(P, 1).nsel))) return rc;
+    *sc = Scratch{P->d_Jc, P->d_Kc, P->d_Dc, P->d_jp, P->d_dmax, P->d_nsel};
+    return 0;
+}
+
+// Quartets each launch of the last build evaluated, [class][precision][kind]
+// (device counters summed over their slots, or the host's count).
+static int launch_counts(const jk_plan *P, std::vector<int64_t> *out) {
+    const size_t nl = P->cls.size() * 8, per = (size_t)NSEL_SLOTS * NSEL_STRIDE;
+    std::vector<unsigned long long> raw(nl * per);
+    HIPCHK(hipMemcpy(raw.data(), P->last_nsel, sizeof(unsigned long long) * raw.size(), hipMemcpyDeviceToHost));
+    out->assign(nl, 0);
+    for (size_t k = 0; k < nl; ++k) {
+        if (k < P->last_fixed.size() && P->last_fixed[k] >= 0) {
+            (*out)[k] = P->last_fixed[k];
+            continue;
+        }
+        int64_t s = 0;
+        for (int j = 0; j < NSEL_SLOTS; ++j) s += (int64_t)raw[k * per + (size_t)j * NSEL_STRIDE];
+        (*out)[k] = s;
     }
     return 0;
 }
 
-extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision, double mix_threshold,
-                          double omega, double *J, double *K, void *stream) {
+__global__ void k_fill_u64(unsigned long long *p, int n) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0ull;
+}
+
+int check_execute_args(const jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision,
+                              double mix_threshold, double omega, double *J, double *K) {
     if (!P) return fail(JK_EINVAL, "plan is NULL");
     if (!D || nset < 1) return fail(JK_EINVAL, "D must be non-NULL and nset >= 1");
     const bool do_j = flags & JK_DO_J, do_k = flags & JK_DO_K;
-    if (flags & ~(JK_DO_J | JK_DO_K | JK_ACCUMULATE)) return fail(JK_EINVAL, "unknown flag bits 0x%x", flags);
+    if (flags & ~(JK_DO_J | JK_DO_K | JK_ACCUMULATE | JK_CHECK_SYMMETRY)) return fail(JK_EINVAL, "unknown flag bits 0x%x", flags);
     if ((do_j && !J) || (do_k && !K)) return fail(JK_EINVAL, "J/K output missing for a requested matrix");
     if (precision != JK_FP64 && precision != JK_MIXED && precision != JK_FP32) return fail(JK_EINVAL, "bad precision %d", precision);
     if (precision == JK_MIXED && !(std::isfinite(mix_threshold) && mix_threshold >= 0.0)) return fail(JK_EINVAL, "mix_threshold must be finite and >= 0");
@@ -789,69 +865,112 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     if (dev != P->device) return fail(JK_EINVAL, "plan was created on device %d, current device is %d", P->device, dev);
-    hipStream_t s = (hipStream_t)stream;
+    return 0;
+}
+
+// max |D - D^T| and max |D| over every density, on the device; the host
+// compares them (JK_CHECK_SYMMETRY).  out[0] = asymmetry, out[1] = largest.
+__global__ void k_symmetry(const double *D, int n, int nset, unsigned long long *out) {
+    const int64_t tot = (int64_t)nset * n * n;
+    double asym = 0.0, big = 0.0;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = t / ((int64_t)n * n);
+        const int i = (int)((t / n) % n), j = (int)(t % n);
+        const double v = D[t];
+        asym = fmax(asym, fabs(v - D[s * n * n + (int64_t)j * n + i]));
+        // a non-finite entry makes the largest magnitude infinite
+        big = fmax(big, isfinite(v) ? fabs(v) : INFINITY);
+    }
+    // non-negative doubles order like their bit patterns
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(asym));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(big));
+}
+
+static int check_symmetry(const jk_plan *P, const double *D, int nset, hipStream_t s, unsigned long long *scratch2) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, scratch2, 2);
+    hipLaunchKernelGGL(k_symmetry, dim3(grid_for((int64_t)nset * P->nao * P->nao, 256)), dim3(256), 0, s, D, P->nao, nset, scratch2);
+    HIPCHK(hipGetLastError());
+    unsigned long long h[2];
+    HIPCHK(hipMemcpyAsync(h, scratch2, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double asym, big;
+    std::memcpy(&asym, &h[0], sizeof asym);
+    std::memcpy(&big, &h[1], sizeof big);
+    if (!(std::isfinite(asym) && std::isfinite(big))) return fail(JK_EINVAL, "D holds non-finite values");
+    if (asym > 1e-12 * big) return fail(JK_EINVAL, "D is not symmetric: max|D - D^T| = %.3e, max|D| = %.3e", asym, big);
+    return 0;
+}
+
+// One J/K build into the given scratch (both entry points).
+int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision, double mix_threshold,
+                        double omega, double *J, double *K, hipStream_t s, const Scratch &sc, bool allow_profile) {
+    const bool do_j = flags & JK_DO_J, do_k = flags & JK_DO_K;
     int rc;
-    if ((rc = ensure_scratch(P, nset, P->sph))) return rc;
+    if ((flags & JK_CHECK_SYMMETRY) && (rc = check_symmetry(P, D, nset, s, sc.nsel))) return rc;
     const size_t m = (size_t)P->naoc * P->naoc;
     const double *Dc = D;
     if (P->sph) {
-        hipLaunchKernelGGL(k_sph_to_cart, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->maps, D, P->d_Dc, P->nao, P->naoc, nset);
+        hipLaunchKernelGGL(k_sph_to_cart, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->maps, D, sc.Dc, P->nao, P->naoc, nset);
         HIPCHK(hipGetLastError());
-        Dc = P->d_Dc;
+        Dc = sc.Dc;
     }
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Jc, (int64_t)(nset * m), 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->d_Kc, (int64_t)(nset * m), 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * P->njp, 256)), dim3(256), 0, s, P->d_jp, (int64_t)nset * P->njp, 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, sc.Jc, (int64_t)(nset * m), 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, sc.Kc, (int64_t)(nset * m), 0.0);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * P->njp, 256)), dim3(256), 0, s, sc.jp, (int64_t)nset * P->njp, 0.0);
+    const int nctr = (int)scratch_sizes(P, nset).nsel;
+    hipLaunchKernelGGL(k_fill_u64, dim3((nctr + 255) / 256), dim3(256), 0, s, sc.nsel, nctr);
     HIPCHK(hipGetLastError());
     if (precision == JK_MIXED || P->dscreen > 0.0) {
-        hipLaunchKernelGGL(k_dmax, dim3((P->ns * P->ns + 255) / 256), dim3(256), 0, s, Dc, P->maps.aoc, P->maps.l, P->ns, P->naoc, nset, P->d_dmax);
+        hipLaunchKernelGGL(k_dmax, dim3((P->ns * P->ns + 255) / 256), dim3(256), 0, s, Dc, P->maps.aoc, P->maps.l, P->ns, P->naoc, nset, sc.dmax);
+        hipLaunchKernelGGL(k_dmax_all, dim3(1), dim3(256), 0, s, sc.dmax, P->ns);
         HIPCHK(hipGetLastError());
     }
     JkArgs a{};
     a.pairs = P->d_pairs;
     a.pp = P->d_pp;
     a.D = Dc;
-    a.J = P->d_Jc;
-    a.K = P->d_Kc;
+    a.J = sc.Jc;
+    a.K = sc.Kc;
     a.mstride = (int64_t)m;
-    a.jp = P->d_jp;
+    a.jp = sc.jp;
     a.jpstride = P->njp;
     a.nao = P->naoc;
     a.nset = nset;
     a.do_j = do_j;
     a.do_k = do_k;
-    a.dmax = P->d_dmax;
+    a.dmax = sc.dmax;
     a.nshell = P->ns;
     a.mix_thr = mix_threshold;
     a.omega = omega;
     a.dscreen = P->dscreen;
     a.tab = P->tab;
-    if (precision == JK_MIXED) {
-        if (!P->d_list) {
-            if ((rc = P->alloc(&P->d_list, (size_t)2 * std::max<int64_t>(P->stats.nquartets, 1))) ||
-                (rc = P->alloc(&P->d_list_cnt, std::max<size_t>(P->cls.size(), 1))))
-                return rc;
-        }
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, s, P->d_list_cnt, (int)P->cls.size());
-        HIPCHK(hipGetLastError());
-    }
-    P->last_mixed = precision == JK_MIXED;
-    // launches in order: (class, precision) -> timing slot
-    std::vector<std::pair<int, int64_t>> slots;  // (timing slot, quartets of the launch)
+    a.tpos = P->d_tpos;
+    a.aoc = P->maps.aoc;
+    P->last_nsel = sc.nsel;
+    P->last_precision = precision;
+    P->last_fixed.assign(P->cls.size() * 8, 0);
+    // with every quartet selected and no density screening a launch
+    // evaluates exactly its quartets: no device counting
+    const bool count_on_device = precision == JK_MIXED || P->dscreen > 0.0;
+    auto set_count = [&](int slot, int64_t host_count) {
+        a.nsel = count_on_device ? sc.nsel + (size_t)slot * NSEL_SLOTS * NSEL_STRIDE : nullptr;
+        P->last_fixed[slot] = count_on_device ? -1 : host_count;
+    };
+    const bool profile = P->profile && allow_profile;
+    // launches in order: timing slot of each
+    std::vector<int> slots;
     int nev = 0;
-    auto mark = [&](int slot, int64_t nq) -> int {
-        if (!P->profile) return 0;
+    auto mark = [&](int slot) -> int {
+        if (!profile) return 0;
         if ((int)P->events.size() <= nev) {
             hipEvent_t ev;
             HIPCHK(hipEventCreate(&ev));
             P->events.push_back(ev);
         }
         HIPCHK(hipEventRecord(P->events[nev++], s));
-        if (slot >= 0) slots.push_back({slot, nq});
+        if (slot >= 0) slots.push_back(slot);
         return 0;
     };
-    a.tpos = P->d_tpos;
-    a.aoc = P->maps.aoc;
     for (size_t ci = 0; ci < P->cls.size(); ++ci) {
         const ClassTask &c = P->cls[ci];
         const ClassEntry &e = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
@@ -859,82 +978,84 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
         a.same = c.same;
         a.npb = c.npb;
         a.npk = c.npk;
-        // mixed: only the one-root classes are split (their FP32 kernels read
-        // a third of the FP64 Boys row); the others run in FP64 throughout
-        const bool split = precision == JK_MIXED && mixed_split_class(c.li, c.lj, c.lk, c.ll);
-        const int pr = precision == JK_FP64 || (precision == JK_MIXED && !split) ? 0 : 1;
-        const int f = c.fam[pr];
-        a.sel = split ? SEL_LOW : SEL_ALL;
-        a.list = P->d_list ? P->d_list + 2 * c.list_off : nullptr;
-        a.list_count = P->d_list_cnt ? P->d_list_cnt + ci : nullptr;
         a.nq = (int32_t)c.nq;
-        const int slot = (int)(2 * ci + pr) * 4;  // + kind
-        const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
-        const bool longrows = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
-                              row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
-        const bool shortrows = c.row_short[pr] && c.nsrow > 0 && e.srow[f - 1][pr] && (longrows || c.nrow == 0) &&
-                               row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 1, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
-        if (longrows || shortrows) {
-            a.bra_list = c.d_bra;
-            a.bra_cnt = c.d_cnt;
-            a.tshK = c.d_tshK;
-            a.tshL = c.d_tshL;
-            a.ncolK = c.ncolK;
-            a.ncolL = c.ncolL;
-            a.seg_same = c.seg_same;
-        }
-        if (longrows) {
-            // long bras: 256-lane workgroups over chunks of their kets
-            a.row_pos = c.d_rowc[f - 1];
-            a.nrow = c.nrowc[f - 1];
-            if ((rc = mark(slot + 1, c.nq_row))) return rc;
-            HIPCHK(e.row[f - 1][pr](a, s));
-        }
-        if (shortrows) {
-            // short bras: one 64-lane workgroup each
-            a.row_pos = c.d_srowt;
-            a.nrow = c.nsrow;
-            if ((rc = mark(slot + 3, c.nq - c.nq_row))) return rc;
-            HIPCHK(e.srow[f - 1][pr](a, s));
-            a.ntiles = 0;
-        } else if (longrows) {
-            // the short rest as tiles
-            a.bra_list = c.d_sbra;
-            a.bra_cnt = c.d_scnt;
-            a.nbra = c.nsbra;
-            a.tile_off = c.d_stile[f - 1];
-            a.ntiles = c.nstiles[f - 1];
-        } else {
-            a.bra_list = c.d_bra;
-            a.bra_cnt = c.d_cnt;
-            a.nbra = c.nbra;
-            a.tile_off = c.d_tile[f - 1];
-            a.ntiles = c.ntiles[f - 1];
-        }
-        if (a.ntiles > 0) {
-            if ((rc = mark(slot, longrows ? c.nq - c.nq_row : c.nq))) return rc;
-            HIPCHK(e.tiles[f - 1][pr](a, s));
-        }
-        if (split) {
-            // the FP32 passes above diverted large-bound quartets to the
-            // list; the FP64 list pass follows
-            const int f64 = c.fam[0];
-            if ((rc = mark((int)(2 * ci) * 4 + 2, 0))) return rc;
-            HIPCHK(e.list64[f64 - 1](a, s));
+        // mixed: a single-precision pass over the quartets below the
+        // threshold, then a double-precision pass over the rest; both walk
+        // the class's tiles and row tasks
+        const int npass = precision == JK_MIXED ? 2 : 1;
+        for (int pass = 0; pass < npass; ++pass) {
+            const int pr = precision == JK_MIXED ? (pass == 0 ? 1 : 0) : (precision == JK_FP32 ? 1 : 0);
+            a.sel = precision == JK_MIXED ? (pass == 0 ? SEL_LO : SEL_HI) : SEL_ALL;
+            const int f = c.fam[pr];
+            // tiles (the short rest) of family 3 classes run in the fallback family
+            const int ft = f == 3 ? tile_fallback(c.li, c.lj, c.lk, c.ll) : f;
+            const int slot = (int)(2 * ci + pr) * 4;  // + kind
+            const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
+            const bool longrows = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
+                                  row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
+            const bool shortrows = c.row_short[pr] && c.nsrow > 0 && e.srow[f - 1][pr] && (longrows || c.nrow == 0) &&
+                                   row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 1, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
+            if (longrows || shortrows) {
+                a.bra_list = c.d_bra;
+                a.bra_cnt = c.d_cnt;
+                a.tshK = c.d_tshK;
+                a.tshL = c.d_tshL;
+                a.ncolK = c.ncolK;
+                a.ncolL = c.ncolL;
+                a.seg_same = c.seg_same;
+            }
+            if (longrows) {
+                // long bras: 256-lane workgroups over chunks of their kets
+                a.row_pos = c.d_rowc[f - 1];
+                a.nrow = c.nrowc[f - 1];
+                set_count(slot + 1, c.nq_row);
+                if ((rc = mark(slot + 1))) return rc;
+                HIPCHK(e.row[f - 1][pr](a, s));
+            }
+            if (shortrows) {
+                // short bras: one 64-lane workgroup each
+                a.row_pos = c.d_srowt;
+                a.nrow = c.nsrow;
+                set_count(slot + 3, c.nq - c.nq_row);
+                if ((rc = mark(slot + 3))) return rc;
+                HIPCHK(e.srow[f - 1][pr](a, s));
+                a.ntiles = 0;
+            } else if (longrows) {
+                // the short rest as tiles
+                a.bra_list = c.d_sbra;
+                a.bra_cnt = c.d_scnt;
+                a.nbra = c.nsbra;
+                a.tile_off = c.d_stile[ft - 1];
+                a.ntiles = c.nstiles[ft - 1];
+            } else {
+                a.bra_list = c.d_bra;
+                a.bra_cnt = c.d_cnt;
+                a.nbra = c.nbra;
+                a.tile_off = c.d_tile[ft - 1];
+                a.ntiles = c.ntiles[ft - 1];
+            }
+            if (a.ntiles > 0) {
+                set_count(slot, longrows ? c.nq - c.nq_row : c.nq);
+                if ((rc = mark(slot))) return rc;
+                HIPCHK(e.tiles[ft - 1][pr](a, s));
+            }
         }
     }
-    if (P->profile) {
-        if ((rc = mark(-1, 0))) return rc;
+    if (profile) {
+        if ((rc = mark(-1))) return rc;
         HIPCHK(hipEventSynchronize(P->events[nev - 1]));
+        std::vector<int64_t> cnt;
+        if ((rc = launch_counts(P, &cnt))) return rc;
         for (size_t k = 0; k < slots.size(); ++k) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, P->events[k], P->events[k + 1]));
-            jk_class_timing &t = P->timing[slots[k].first];
-            const ClassTask &c = P->cls[slots[k].first / 8];
+            jk_class_timing &t = P->timing[slots[k]];
+            const ClassTask &c = P->cls[slots[k] / 8];
+            const int64_t nq = cnt[slots[k]];
             t.ms += ms;
             t.launches += 1;
-            t.nquartets += slots[k].second;
-            t.model_flops += c.flops * (double)slots[k].second / (double)c.nq;
+            t.nquartets += nq;
+            t.model_flops += c.flops * (double)nq / (double)c.nq;
         }
     }
     const int acc = (flags & JK_ACCUMULATE) ? 1 : 0;
@@ -942,13 +1063,22 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     const int npair = (int)P->hpairs.size();
     if (do_j) {
         const int64_t nt = (int64_t)nset * npair * 64;
-        hipLaunchKernelGGL(k_jp_scatter, dim3(grid_for(nt, 256)), dim3(256), 0, s, P->d_pairs, P->maps.l, P->d_jp, P->njp,
-                           P->d_Jc, (int64_t)m, P->naoc, npair, nt);
+        hipLaunchKernelGGL(k_jp_scatter, dim3(grid_for(nt, 256)), dim3(256), 0, s, P->d_pairs, P->maps.l, sc.jp, P->njp,
+                           sc.Jc, (int64_t)m, P->naoc, npair, nt);
     }
-    if (do_j) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Jc, J, P->nao, P->naoc, nset, P->sph, acc);
-    if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, P->d_Kc, K, P->nao, P->naoc, nset, P->sph, acc);
+    if (do_j) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, sc.Jc, J, P->nao, P->naoc, nset, P->sph, acc);
+    if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, sc.Kc, K, P->nao, P->naoc, nset, P->sph, acc);
     HIPCHK(hipGetLastError());
     return JK_OK;
+}
+
+extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision, double mix_threshold,
+                          double omega, double *J, double *K, void *stream) {
+    int rc = check_execute_args(P, D, nset, flags, precision, mix_threshold, omega, J, K);
+    if (rc) return rc;
+    Scratch sc;
+    if ((rc = ensure_scratch(P, nset, &sc))) return rc;
+    return execute_impl(P, D, nset, flags, precision, mix_threshold, omega, J, K, (hipStream_t)stream, sc, true);
 }
 
 extern "C" int jk_plan_set_density_screening(jk_plan *P, double threshold) {
@@ -970,7 +1100,8 @@ extern "C" int jk_plan_profile(jk_plan *P, int32_t enable) {
                 t.li = c.li; t.lj = c.lj; t.lk = c.lk; t.ll = c.ll;
                 t.npb = c.npb; t.npk = c.npk;
                 t.precision = (k && kind != 2) ? JK_FP32 : JK_FP64;
-                t.family = kind == 2 ? c.fam[0] : c.fam[k];
+                // tiles of a family-3 class run in its fallback family
+                t.family = kind == 0 && c.fam[k] == 3 ? tile_fallback(c.li, c.lj, c.lk, c.ll) : c.fam[k];
                 t.kind = kind;
             }
     return 0;

@@ -32,7 +32,7 @@ struct MolDesc {
     double *jp;              // pair-ordered J'_KL [nset][njp]
     const PairRec *pairs;
     int64_t njp;
-    float *dmax;             // [ns][ns]
+    double *dmax;            // [ns][ns]
     int32_t nao, naoc, ns, sph, npair;
 };
 
@@ -64,6 +64,21 @@ __global__ void kb_dmax(const MolDesc *mols, int nset) {
         m.dmax[t] = dmax_elem(m.Dc, m.maps.aoc, m.maps.l, m.ns, m.naoc, nset, t);
 }
 
+// m.dmax[ns * ns] = the largest entry of molecule m's table (one workgroup each).
+__global__ void __launch_bounds__(256) kb_dmax_all(const MolDesc *mols) {
+    const MolDesc &m = mols[blockIdx.x];
+    __shared__ double part[256];
+    double v = 0.0;
+    for (int t = threadIdx.x; t < m.ns * m.ns; t += 256) v = fmax(v, m.dmax[t]);
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) m.dmax[m.ns * m.ns] = part[0];
+}
+
 __global__ void kb_finalize(const MolDesc *mols, int nset) {
     const MolDesc &m = mols[blockIdx.y];
     const int64_t tot = (int64_t)nset * m.nao * m.nao;
@@ -73,20 +88,19 @@ __global__ void kb_finalize(const MolDesc *mols, int nset) {
     }
 }
 
-__global__ void kb_zero_i32(int32_t *p, int n) {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0;
+__global__ void kb_zero_u64(unsigned long long *p, int n) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0ull;
 }
 
 // One launch: the descriptors [first, first + count) of one (class, family)
 // group.
 struct Group {
-    int cid, fam, fam64;
-    int pr, split;     // kernel precision (0 FP64, 1 FP32); mixed split with list pass
+    int cid, fam;
+    int pr, sel;       // kernel precision (0 FP64, 1 FP32); quartet selection (SEL_*)
     int kind;          // 0: tiles, 1: 64-lane row tasks
     size_t lds;        // row tasks: largest dynamic LDS over the descriptors
     int first, count;
     int total_tiles;
-    int64_t list_cap;  // mixed: summed list capacity of the descriptors
     double work;       // model FLOPs of the group, for launch order
 };
 
@@ -101,7 +115,8 @@ struct jk_batch {
     std::vector<BatchDesc> hdesc;
     BatchDesc *d_desc = nullptr;
     std::vector<Group> groups;
-    int32_t *d_ctr = nullptr;  // mixed split: list counts per (molecule, class)
+    unsigned long long *d_ctr = nullptr;  // evaluated quartets per descriptor (NSEL_SLOTS counters each)
+    std::vector<int64_t> fixed;           // per descriptor: its quartet count when not counted on the device
     int32_t *d_tasks = nullptr;  // row tasks of the row-kind descriptors
     int nctr = 0;
     int64_t max_elems = 0;      // largest nset * naoc^2 over the molecules
@@ -140,12 +155,13 @@ static int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int6
 static int record(jk_batch *b) {
     const int nm = b->nmol;
     hipStream_t s = b->cap;
-    hipLaunchKernelGGL(kb_zero_i32, dim3(grid_rows(b->nctr)), dim3(256), 0, s, b->d_ctr, b->nctr);
+    hipLaunchKernelGGL(kb_zero_u64, dim3(grid_rows(b->nctr)), dim3(256), 0, s, b->d_ctr, b->nctr);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(kb_prepare, dim3(grid_rows(b->max_elems), nm), dim3(256), 0, s, b->d_mol, b->nset);
     HIPCHK(hipGetLastError());
     if (b->precision == JK_MIXED) {
         hipLaunchKernelGGL(kb_dmax, dim3(grid_rows(b->max_ns2), nm), dim3(256), 0, s, b->d_mol, b->nset);
+        hipLaunchKernelGGL(kb_dmax_all, dim3(nm), dim3(256), 0, s, b->d_mol);
         HIPCHK(hipGetLastError());
     }
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
@@ -153,7 +169,6 @@ static int record(jk_batch *b) {
         const ClassEntry &e = g_classes[g.cid];
         if (g.kind == 1) HIPCHK(e.batch_row[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, g.lds, s));
         else HIPCHK(e.batch[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, s));
-        if (g.split) HIPCHK(e.batch_list[g.fam64 - 1](b->d_desc + g.first, g.count, g.list_cap, s));
     }
     hipLaunchKernelGGL(kb_jp_scatter, dim3(grid_rows(b->max_jpt), nm), dim3(256), 0, s, b->d_mol, b->nset);
     HIPCHK(hipGetLastError());
@@ -188,32 +203,32 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
     int rc;
 
     // per-molecule scratch, one allocation each kind
-    std::vector<int64_t> eoff(nmol + 1, 0), soff(nmol + 1, 0), loff(nmol + 1, 0), coff(nmol + 1, 0), joff(nmol + 1, 0);
+    std::vector<int64_t> eoff(nmol + 1, 0), soff(nmol + 1, 0), joff(nmol + 1, 0);
     for (int m = 0; m < nmol; ++m) {
         const jk_plan *P = plans[m];
         const int64_t e = (int64_t)nset * P->naoc * P->naoc;
         eoff[m + 1] = eoff[m] + e;
         joff[m + 1] = joff[m] + (int64_t)nset * P->njp;
         b->max_jpt = std::max(b->max_jpt, (int64_t)nset * (int64_t)P->hpairs.size() * 64);
-        soff[m + 1] = soff[m] + (int64_t)P->ns * P->ns;
-        loff[m + 1] = loff[m] + 2 * std::max<int64_t>(P->stats.nquartets, 1);
-        coff[m + 1] = coff[m] + (int64_t)P->cls.size();
+        soff[m + 1] = soff[m] + (int64_t)P->ns * P->ns + 1;  // the table and its largest entry
         b->max_elems = std::max(b->max_elems, e);
         b->max_ns2 = std::max(b->max_ns2, P->ns * P->ns);
     }
     double *Dc, *Jc, *Kc, *jp;
-    float *dmax = nullptr;
-    int32_t *list = nullptr;
+    double *dmax = nullptr;
     if ((rc = b->alloc(&Dc, eoff[nmol])) || (rc = b->alloc(&Jc, eoff[nmol])) || (rc = b->alloc(&Kc, eoff[nmol])) ||
         (rc = b->alloc(&jp, joff[nmol])))
         return rc;
-    if (precision == JK_MIXED && ((rc = b->alloc(&dmax, soff[nmol])) || (rc = b->alloc(&list, loff[nmol])))) return rc;
+    if (precision == JK_MIXED && (rc = b->alloc(&dmax, soff[nmol]))) return rc;
 
-    // descriptors grouped by (class, family, kind); heavy molecules first.
-    // Unless row mode is off for the class, every bra runs as 64-lane row
-    // tasks (K rows in LDS): the small molecules of a batch have few long
-    // bras, and per-quartet K atomics would dominate.
-    using Key = std::tuple<int, int, int, int, int, int>;  // class, family, FP64 family, kind, precision, split
+    // descriptors grouped by (class, family, kind, precision, selection);
+    // heavy molecules first.  Unless row mode is off for the class, every
+    // bra runs as 64-lane row tasks (K rows in LDS): the small molecules of
+    // a batch have few long bras, and per-quartet K atomics would dominate.
+    // Mixed precision: two descriptors per (molecule, class), the
+    // single-precision pass over the quartets below the threshold and the
+    // double-precision pass over the rest.
+    using Key = std::tuple<int, int, int, int, int>;  // class, family, kind, precision, selection
     std::map<Key, std::vector<std::pair<double, BatchDesc>>> byg;
     std::vector<int32_t> alltasks;
     std::map<Key, size_t> glds;
@@ -238,70 +253,73 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         md.sph = P->sph;
         for (size_t ci = 0; ci < P->cls.size(); ++ci) {
             const ClassTask &c = P->cls[ci];
-            // mixed: only the one-root classes are split (as in jk_execute)
-            const bool split = precision == JK_MIXED && mixed_split_class(c.li, c.lj, c.lk, c.ll);
-            const int pr = precision == JK_FP64 || (precision == JK_MIXED && !split) ? 0 : 1;
-            const int f = c.fam[pr];
-            if (c.ntiles[f - 1] <= 0) continue;
-            const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
-            const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
-            const size_t lds1 = row_lds_bytes(ce, f, pr, c.li, c.lj, nset, ncols, 1, c.npb);
-            const int kind = c.row_ok[pr] && ce.batch_row[f - 1][pr] && lds1 <= (size_t)ROW_LDS_MAX ? 1 : 0;
-            BatchDesc d{};
-            JkArgs &a = d.a;
-            a.pairs = P->d_pairs;
-            a.pp = P->d_pp;
-            a.bra_list = c.d_bra;
-            a.bra_cnt = c.d_cnt;
-            a.nbra = c.nbra;
-            a.tile_off = c.d_tile[f - 1];
-            a.ntiles = c.ntiles[f - 1];
-            a.ket_list = c.d_ket;
-            a.same = c.same;
-            a.npb = c.npb;
-            a.npk = c.npk;
-            a.nq = (int32_t)c.nq;
-            a.list = list ? list + loff[m] + 2 * c.list_off : nullptr;
-            a.list_count = nullptr;  // set below, after the counter layout is known
-            a.tpos = P->d_tpos;
-            a.aoc = P->maps.aoc;
-            a.D = md.Dc;
-            a.J = md.Jc;
-            a.K = md.Kc;
-            a.mstride = (int64_t)P->naoc * P->naoc;
-            a.jp = md.jp;
-            a.jpstride = P->njp;
-            a.nao = P->naoc;
-            a.nset = nset;
-            a.do_j = 1;
-            a.do_k = 1;
-            a.dmax = md.dmax;
-            a.nshell = P->ns;
-            a.sel = split ? SEL_LOW : SEL_ALL;
-            a.mix_thr = mix_threshold;
-            a.tab = P->tab;
-            d.pad[0] = (int32_t)(coff[m] + (int64_t)ci);  // list counter slot (host only)
-            d.pad[1] = a.ntiles;                           // work units (tiles or row tasks)
-            if (kind == 1) {
-                // every bra of the class: long bras in chunks, short ones whole
-                const size_t first = alltasks.size();
-                alltasks.insert(alltasks.end(), c.h_rowc[f - 1].begin(), c.h_rowc[f - 1].end());
-                alltasks.insert(alltasks.end(), c.h_srowt.begin(), c.h_srowt.end());
-                d.pad[1] = (int32_t)((alltasks.size() - first) / 3);
-                d.pad[2] = (int32_t)first;                 // offset into the task buffer (host only)
-                a.nrow = d.pad[1];
-                a.tshK = c.d_tshK;
-                a.tshL = c.d_tshL;
-                a.ncolK = c.ncolK;
-                a.ncolL = c.ncolL;
-                a.seg_same = c.seg_same;
-                if (alltasks.size() > (size_t)INT32_MAX) return fail(JK_EINVAL, "too many row tasks");
+            const int npass = precision == JK_MIXED ? 2 : 1;
+            for (int pass = 0; pass < npass; ++pass) {
+                const int pr = precision == JK_MIXED ? (pass == 0 ? 1 : 0) : (precision == JK_FP32 ? 1 : 0);
+                const int sel = precision == JK_MIXED ? (pass == 0 ? SEL_LO : SEL_HI) : SEL_ALL;
+                int f = c.fam[pr];
+                const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
+                const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
+                const size_t lds1 = row_lds_bytes(ce, f, pr, c.li, c.lj, nset, ncols, 1, c.npb);
+                const int kind = c.row_ok[pr] && ce.batch_row[f - 1][pr] && lds1 <= (size_t)ROW_LDS_MAX ? 1 : 0;
+                // tiles of a family-3 class run in its fallback family
+                if (kind == 0 && f == 3) f = tile_fallback(c.li, c.lj, c.lk, c.ll);
+                if (c.nq <= 0) continue;
+                BatchDesc d{};
+                JkArgs &a = d.a;
+                a.pairs = P->d_pairs;
+                a.pp = P->d_pp;
+                a.bra_list = c.d_bra;
+                a.bra_cnt = c.d_cnt;
+                a.nbra = c.nbra;
+                if (kind == 0) {  // (f <= 2 here)
+                    a.tile_off = c.d_tile[f - 1];
+                    a.ntiles = c.ntiles[f - 1];
+                }
+                a.ket_list = c.d_ket;
+                a.same = c.same;
+                a.npb = c.npb;
+                a.npk = c.npk;
+                a.nq = (int32_t)c.nq;
+                a.tpos = P->d_tpos;
+                a.aoc = P->maps.aoc;
+                a.D = md.Dc;
+                a.J = md.Jc;
+                a.K = md.Kc;
+                a.mstride = (int64_t)P->naoc * P->naoc;
+                a.jp = md.jp;
+                a.jpstride = P->njp;
+                a.nao = P->naoc;
+                a.nset = nset;
+                a.do_j = 1;
+                a.do_k = 1;
+                a.dmax = md.dmax;
+                a.nshell = P->ns;
+                a.sel = sel;
+                a.mix_thr = mix_threshold;
+                a.tab = P->tab;
+                d.pad[1] = a.ntiles;  // work units (tiles or row tasks)
+                if (kind == 1) {
+                    // every bra of the class: long bras in chunks, short ones whole
+                    const size_t first = alltasks.size();
+                    alltasks.insert(alltasks.end(), c.h_rowc[f - 1].begin(), c.h_rowc[f - 1].end());
+                    alltasks.insert(alltasks.end(), c.h_srowt.begin(), c.h_srowt.end());
+                    d.pad[1] = (int32_t)((alltasks.size() - first) / 3);
+                    d.pad[2] = (int32_t)first;  // offset into the task buffer (host only)
+                    a.nrow = d.pad[1];
+                    a.tshK = c.d_tshK;
+                    a.tshL = c.d_tshL;
+                    a.ncolK = c.ncolK;
+                    a.ncolL = c.ncolL;
+                    a.seg_same = c.seg_same;
+                    if (alltasks.size() > (size_t)INT32_MAX) return fail(JK_EINVAL, "too many row tasks");
+                }
+                if (!(kind == 1 || ce.batch[f - 1][pr]))
+                    return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has no batched kernel", c.li, c.lj, c.lk, c.ll);
+                const Key key = std::make_tuple(class_id(c.li, c.lj, c.lk, c.ll), f, kind, pr, sel);
+                byg[key].push_back({c.flops, d});
+                if (kind == 1) glds[key] = std::max(glds[key], lds1);
             }
-            if (!(kind == 1 || ce.batch[f - 1][pr]) || (split && !ce.batch_list[c.fam[0] - 1]))
-                return fail(JK_EUNSUPPORTED, "class (%d%d|%d%d) has no batched kernel", c.li, c.lj, c.lk, c.ll);
-            const Key key = std::make_tuple(class_id(c.li, c.lj, c.lk, c.ll), f, c.fam[0], kind, pr, split ? 1 : 0);
-            byg[key].push_back({c.flops, d});
-            if (kind == 1) glds[key] = std::max(glds[key], lds1);
         }
     }
     for (auto &kv : byg) {
@@ -310,10 +328,9 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         Group g{};
         g.cid = std::get<0>(kv.first);
         g.fam = std::get<1>(kv.first);
-        g.fam64 = std::get<2>(kv.first);
-        g.kind = std::get<3>(kv.first);
-        g.pr = std::get<4>(kv.first);
-        g.split = std::get<5>(kv.first);
+        g.kind = std::get<2>(kv.first);
+        g.pr = std::get<3>(kv.first);
+        g.sel = std::get<4>(kv.first);
         g.lds = g.kind == 1 ? glds[kv.first] : 0;
         g.first = (int)b->hdesc.size();
         g.count = (int)v.size();
@@ -321,7 +338,6 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         for (auto &x : v) {
             x.second.tile_base = (int32_t)tiles;
             tiles += x.second.pad[1];
-            g.list_cap += x.second.a.nq;
             g.work += x.first;
             b->hdesc.push_back(x.second);
         }
@@ -330,8 +346,11 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         b->groups.push_back(g);
     }
     std::stable_sort(b->groups.begin(), b->groups.end(), [](const Group &x, const Group &y) { return x.work > y.work; });
-    // one list count per (molecule, class); row tasks to the device
-    b->nctr = (int)coff[nmol];
+    // evaluated-quartet counters per descriptor (mixed precision only: with
+    // every quartet selected the count is the descriptor's); row tasks to
+    // the device
+    const size_t per = (size_t)NSEL_SLOTS * NSEL_STRIDE;
+    b->nctr = (int)(std::max<size_t>(b->hdesc.size(), 1) * per);
     if ((rc = b->alloc(&b->d_ctr, b->nctr))) return rc;
     if ((rc = b->alloc(&b->d_tasks, alltasks.size()))) return rc;
     if (!alltasks.empty())
@@ -343,8 +362,15 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             if (g.kind == 1) d.a.row_pos = b->d_tasks + d.pad[2];
         }
     }
-    for (BatchDesc &d : b->hdesc) {
-        d.a.list_count = precision == JK_MIXED ? b->d_ctr + d.pad[0] : nullptr;
+    b->fixed.assign(b->hdesc.size(), -1);
+    for (size_t k = 0; k < b->hdesc.size(); ++k) {
+        BatchDesc &d = b->hdesc[k];
+        if (precision == JK_MIXED) {
+            d.a.nsel = b->d_ctr + k * per;
+        } else {
+            d.a.nsel = nullptr;
+            b->fixed[k] = d.a.nq;
+        }
         d.pad[0] = d.pad[1] = d.pad[2] = 0;
     }
     if ((rc = b->alloc(&b->d_desc, b->hdesc.size())) || (rc = b->alloc(&b->d_mol, nmol))) return rc;
@@ -363,10 +389,12 @@ extern "C" int jk_batch_execute(jk_batch *b, const double *const *D, double *con
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     if (dev != b->device) return fail(JK_EINVAL, "batch was created on device %d, current device is %d", b->device, dev);
+    // every pointer is checked before the cached table changes
+    for (int m = 0; m < b->nmol; ++m)
+        if (!D[m] || !J[m] || !K[m]) return fail(JK_EINVAL, "molecule %d: NULL D, J or K", m);
     hipStream_t s = (hipStream_t)stream;
     bool changed = false;
     for (int m = 0; m < b->nmol; ++m) {
-        if (!D[m] || !J[m] || !K[m]) return fail(JK_EINVAL, "molecule %d: NULL D, J or K", m);
         MolDesc &md = b->hmol[m];
         if (md.D != D[m] || md.J != J[m] || md.K != K[m]) {
             md.D = D[m];
@@ -396,6 +424,30 @@ extern "C" int jk_batch_execute(jk_batch *b, const double *const *D, double *con
         HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     }
     HIPCHK(hipGraphLaunch(b->exec, s));
+    return JK_OK;
+}
+
+extern "C" int jk_batch_stats(const jk_batch *b, int64_t *nquartets, int64_t *nquartets_fp32) {
+    if (!b) return fail(JK_EINVAL, "batch is NULL");
+    const size_t per = (size_t)NSEL_SLOTS * NSEL_STRIDE;
+    std::vector<unsigned long long> raw(b->hdesc.size() * per);
+    HIPCHK(hipDeviceSynchronize());
+    if (!raw.empty())
+        HIPCHK(hipMemcpy(raw.data(), b->d_ctr, sizeof(unsigned long long) * raw.size(), hipMemcpyDeviceToHost));
+    int64_t n = 0, n32 = 0;
+    for (const Group &g : b->groups)
+        for (int k = 0; k < g.count; ++k) {
+            const size_t d = (size_t)(g.first + k);
+            int64_t c = b->fixed[d];
+            if (c < 0) {
+                c = 0;
+                for (int j = 0; j < NSEL_SLOTS; ++j) c += (int64_t)raw[d * per + (size_t)j * NSEL_STRIDE];
+            }
+            n += c;
+            if (g.pr == 1) n32 += c;
+        }
+    if (nquartets) *nquartets = n;
+    if (nquartets_fp32) *nquartets_fp32 = n32;
     return JK_OK;
 }
 

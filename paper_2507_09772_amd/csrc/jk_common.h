@@ -53,14 +53,23 @@ struct PrimPair {
     double PA[3];   // P - A
 };
 
-// Kernel families per angular class (both are built where both fit; the
-// planner picks one per class and precision from the tuning table):
+// Kernel families per angular class (all that fit are built; the planner
+// picks one per class and precision from the tuning table):
 //   1: one lane per quartet (register-resident integral block);
 //   2: a lane group per quartet, 2-D integrals staged in LDS.
 JK_HD constexpr int ncart4(int li, int lj, int lk, int ll) { return ncart(li) * ncart(lj) * ncart(lk) * ncart(ll); }
 JK_HD constexpr bool has_family1(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) <= 180; }
 JK_HD constexpr bool has_family2(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) >= 18; }
 JK_HD constexpr int default_family(int li, int lj, int lk, int ll) { return ncart4(li, lj, lk, ll) <= 36 ? 1 : 2; }
+//   3: a lane per Cartesian component of the bra's first shell, each lane's
+//      elements in registers, the vertical-recurrence tables in LDS (row
+//      mode only; bras with short ket prefixes fall back to the tiles of
+//      family 2, or 1 where 2 is not built).
+JK_HD constexpr bool has_family3(int li, int lj, int lk, int ll) {
+    return li >= 1 && ncart(lj) * ncart(lk) * ncart(ll) <= 64 && ncart4(li, lj, lk, ll) >= 27;
+}
+JK_HD constexpr int k3_qw(int li) { return 64 / ncart(li); }
+JK_HD constexpr int tile_fallback(int li, int lj, int lk, int ll) { return has_family2(li, lj, lk, ll) ? 2 : 1; }
 // Family 2: lanes per quartet = ncart(li) * ncart(lk) (slot = (a, c)).
 JK_HD constexpr int k2_slots(int li, int lj, int lk, int ll) { return ncart(li) * ncart(lk); }
 JK_HD constexpr int k2_qw(int li, int lj, int lk, int ll) {
@@ -71,23 +80,26 @@ JK_HD constexpr int k2_qw(int li, int lj, int lk, int ll) {
 // bra's kets spread over several workgroups (family 1 computes 256 kets
 // per pass, family 2 four waves of k2_qw quartets).
 JK_HD constexpr int row_chunk(int fam, int li, int lj, int lk, int ll) {
-    return fam == 1 ? 2048 : 256 * k2_qw(li, lj, lk, ll);
+    return fam == 1 ? 2048 : fam == 2 ? 256 * k2_qw(li, lj, lk, ll) : 256 * k3_qw(li);
 }
 // Quartets per wave-tile of a family.
 JK_HD constexpr int quartets_per_tile(int fam, int li, int lj, int lk, int ll) {
     return fam == 1 ? 64 : k2_qw(li, lj, lk, ll);
 }
 
-// Quartet sources: tiles of (bra, Q-sorted ket prefix), an explicit list
-// with digestion (the FP64 part of the mixed split), or an explicit list
-// whose blocks are written out (Schwarz diagonal, test hook).
-enum { MODE_JK = 0, MODE_EXPORT = 1, MODE_LIST = 2 };
+// Quartet sources: tiles of (bra, Q-sorted ket prefix), or an explicit
+// list whose blocks are written out (Schwarz diagonal, test hook).
+enum { MODE_JK = 0, MODE_EXPORT = 1 };
 // Row mode (family 1): one workgroup per bra with a long ket prefix; K rows
 // of the bra's two shells accumulate in LDS over column-compressed segments
 // (the columns of the ket shell types only) and are flushed once.
-// SEL_LOW: FP32 tile pass of the mixed split; quartets whose bound reaches
-// the threshold are appended to the list for the FP64 list pass instead.
-enum { SEL_ALL = 0, SEL_LOW = 1 };
+// Quartet selection of a launch: every quartet, or one side of the mixed
+// precision split by the bound Q_IJ Q_KL max|D_block| against the threshold
+// (SEL_LO: below it, the single-precision pass; SEL_HI: at or above it, the
+// double-precision pass).  Both passes walk the same tiles and row tasks and
+// mask the other side's lanes; a wave with no selected lane skips the work.
+enum { SEL_ALL = 0, SEL_LO = 1, SEL_HI = 2 };
+constexpr int NSEL_SLOTS = 16, NSEL_STRIDE = 8;  // counters per launch, 64 bytes apart
 
 struct Tables {
     const double *rys;     // degree-major Rys fits, FP64
@@ -109,10 +121,11 @@ struct JkArgs {
     const int32_t *q_bra, *q_ket;
     int32_t nq;
     double *out;
-    // mixed split: appended (bra, ket) pair ids and their count; LIST mode
-    // reads them back (nq is the capacity)
-    int32_t *list;
-    int32_t *list_count;
+    // quartets this launch evaluated (after the selection and the density
+    // screening): NSEL_SLOTS counters NSEL_STRIDE apart, picked by workgroup,
+    // so that the waves of a launch do not all add to one address; NULL when
+    // the host knows the count (every quartet selected, no density screening)
+    unsigned long long *nsel;
     // row mode: tasks (list position, ket begin, ket end); column segments of the ket
     // shell types (shells of each type in order; tpos = index of a shell
     // within its type); segment L aliases segment K when the types match
@@ -131,7 +144,8 @@ struct JkArgs {
     int64_t jpstride;
     int32_t nao, nset, do_j, do_k;
     // precision split
-    const float *dmax;   // [nshell][nshell] max |D| over the block and densities
+    const double *dmax;  // [nshell][nshell] max |D| over the block and densities, then
+                         // the largest entry of all (element nshell * nshell)
     int32_t nshell, sel;
     double mix_thr;
     // operator: 0 Coulomb, > 0 erf(omega r)/r, < 0 erfc(|omega| r)/r

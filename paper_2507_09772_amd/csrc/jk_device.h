@@ -79,7 +79,8 @@ template <> struct TabSel<float> {
 // Below the table end both come from the Taylor expansion about the nearest
 // grid point T_j (spacing 1/32), F_m(T) = sum_k F_(m+k)(T_j) (T_j - T)^k / k!,
 // 7 terms in FP64 and 4 in FP32 (no exponential needed).  Above it, the
-// large-T limits F_0 = sqrt(pi/T) / 2 and F_1 = F_0 / (2T).
+// large-T limits F_0 = sqrt(pi/T) / 2 and F_1 = F_0 / (2T), evaluated in FP64
+// in both precisions.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u, R &w) {
@@ -98,9 +99,10 @@ __device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u,
         w = f0;
         u = f1 * rcp_<R>(f0);
     } else {
-        const R rt = rsqrt_<R>((R)T);
-        w = (R)SQRT_PI_HALF * rt;
-        u = (R)0.5 * rt * rt;
+        // large T: the asymptotic Boys values, in FP64 for both precisions
+        const double rt = rsq64(T);
+        w = (R)(SQRT_PI_HALF * rt);
+        u = (R)(0.5 * rt * rt);
     }
 }
 
@@ -143,9 +145,10 @@ __device__ __forceinline__ void rys1_eval(double T, const Rys1Row<R> &row, R &u,
         w = f0;
         u = f1 * rcp_<R>(f0);
     } else {
-        const R rt = rsqrt_<R>((R)T);
-        w = (R)SQRT_PI_HALF * rt;
-        u = (R)0.5 * rt * rt;
+        // large T: the asymptotic Boys values, in FP64 for both precisions
+        const double rt = rsq64(T);
+        w = (R)(SQRT_PI_HALF * rt);
+        u = (R)(0.5 * rt * rt);
     }
 }
 
@@ -257,14 +260,15 @@ __device__ __forceinline__ void rys_roots(double T, const Tables &tab, R (&u)[N]
                 w[i] = acc[N + i];
             }
         } else {
-            const R rt = rsqrt_<R>((R)T);
-            const R rT = rt * rt;
-            const R *hx = TabSel<R>::hx2(tab) + jkt_herm_offset[N];
-            const R *hw = TabSel<R>::hw(tab) + jkt_herm_offset[N];
+            // large T: the Gauss-Hermite limit, in FP64 for both precisions
+            const double rt = rsq64(T);
+            const double rT = rt * rt;
+            const double *hx = tab.hx2 + jkt_herm_offset[N];
+            const double *hw = tab.hw + jkt_herm_offset[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) {
-                u[i] = hx[i] * rT;
-                w[i] = hw[i] * rt;
+                u[i] = (R)(hx[i] * rT);
+                w[i] = (R)(hw[i] * rt);
             }
         }
     }
@@ -321,9 +325,10 @@ __device__ __forceinline__ void rys_root1(double T, int r, const Tables &tab, R 
             u = au;
             w = aw;
         } else {
-            const R rt = rsqrt_<R>((R)T);
-            u = TabSel<R>::hx2(tab)[jkt_herm_offset[N] + r] * rt * rt;
-            w = TabSel<R>::hw(tab)[jkt_herm_offset[N] + r] * rt;
+            // large T: the Gauss-Hermite limit, in FP64 for both precisions
+            const double rt = rsq64(T);
+            u = (R)(tab.hx2[jkt_herm_offset[N] + r] * rt * rt);
+            w = (R)(tab.hw[jkt_herm_offset[N] + r] * rt);
         }
     }
 }
@@ -478,55 +483,53 @@ __device__ __forceinline__ int tile_bra(const int32_t *__restrict__ off, int n, 
     return lo;
 }
 
-__device__ __forceinline__ float dmax6(const JkArgs &a, const PairRec &B, const PairRec &K) {
-    const float *dm = a.dmax;
+__device__ __forceinline__ double dmax6(const JkArgs &a, const PairRec &B, const PairRec &K) {
+    const double *dm = a.dmax;
     const int n = a.nshell;
-    float m = dm[B.ish * n + B.jsh];
-    m = fmaxf(m, dm[K.ish * n + K.jsh]);
-    m = fmaxf(m, dm[B.ish * n + K.ish]);
-    m = fmaxf(m, dm[B.ish * n + K.jsh]);
-    m = fmaxf(m, dm[B.jsh * n + K.ish]);
-    m = fmaxf(m, dm[B.jsh * n + K.jsh]);
+    double m = dm[B.ish * n + B.jsh];
+    m = fmax(m, dm[K.ish * n + K.jsh]);
+    m = fmax(m, dm[B.ish * n + K.ish]);
+    m = fmax(m, dm[B.ish * n + K.jsh]);
+    m = fmax(m, dm[B.jsh * n + K.ish]);
+    m = fmax(m, dm[B.jsh * n + K.jsh]);
     return m;
 }
 
-// Mixed split, FP32 tile pass: a quartet whose bound Q_IJ Q_KL max|D_block|
-// reaches the threshold is appended (bra, ket) to the FP64 list instead.
-// push: lanes that own an append (one per quartet).  Wave-compacted: one
-// counter atomic per wave.
-__device__ __forceinline__ void list_append(const JkArgs &a, bool push, int bra, int ket) {
-    const unsigned long long m = __ballot(push);
-    if (m == 0ull) return;
-    const int lane = lane_index();
-    int base = 0;
-    if (lane == 0) base = atomicAdd(a.list_count, (int)__popcll(m));
-    base = __shfl(base, 0, 64);
-    if (push) {
-        const int idx = base + (int)__popcll(m & ((1ull << lane) - 1ull));
-        if (idx < a.nq) {
-            a.list[2 * idx] = bra;
-            a.list[2 * idx + 1] = ket;
-        }
+// Screening and precision split of one quartet from its bound
+// Q_IJ Q_KL max|D| over the six blocks it touches (FP64): below dscreen
+// (> 0) the quartet is dropped (density screening); the single-precision
+// pass of the mixed split keeps the quartets below mix_thr, the
+// double-precision pass those at or above it.  Both settings are uniform in
+// the launch, so the branch on them is too.
+__device__ __forceinline__ void screen_quartet(const JkArgs &a, const PairRec &B, const PairRec &K, bool &valid) {
+    if (a.dscreen > 0.0 || a.sel != SEL_ALL) {
+        const double bound = B.q * K.q * dmax6(a, B, K);
+        if (a.dscreen > 0.0) valid = valid && bound >= a.dscreen;
+        if (a.sel == SEL_LO) valid = valid && bound < a.mix_thr;
+        else if (a.sel == SEL_HI) valid = valid && bound >= a.mix_thr;
     }
 }
 
-// Screening and precision split of one quartet from its bound
-// Q_IJ Q_KL max|D| over the six blocks it touches: below dscreen (> 0) the
-// quartet is dropped (density screening); in the FP32 pass of the mixed
-// split a quartet at or above mix_thr is marked hi (it goes to the FP64
-// list instead).  Both decisions are uniform in the class, so the branch on
-// them is too.
-__device__ __forceinline__ void screen_quartet(const JkArgs &a, const PairRec &B, const PairRec &K, bool &valid,
-                                               bool &hi) {
-    hi = false;
-    if (a.dscreen > 0.0 || a.sel == SEL_LOW) {
-        const double bound = B.q * K.q * (double)dmax6(a, B, K);
-        if (a.dscreen > 0.0) valid = valid && bound >= a.dscreen;
-        if (a.sel == SEL_LOW) {
-            hi = valid && bound >= a.mix_thr;
-            valid = valid && !hi;
-        }
-    }
+// Whether any quartet of a bra with Schwarz factor qb and a ket with factor
+// at most qk can still be selected, from the largest density block of all:
+// the ket lists are sorted by Schwarz factor (descending), so once this
+// fails for the first ket of a chunk it fails for every later ket of the bra
+// (the double-precision pass of the mixed split, density screening).
+__device__ __forceinline__ bool prefix_selectable(const JkArgs &a, double qb, double qk) {
+    if (a.sel != SEL_HI && a.dscreen <= 0.0) return true;
+    const double b = qb * qk * a.dmax[a.nshell * a.nshell];
+    return (a.sel != SEL_HI || b >= a.mix_thr) && (a.dscreen <= 0.0 || b >= a.dscreen);
+}
+
+// Number of a wave's lanes with mine set (one lane per quartet): the
+// quartets the wave evaluates; a wave with none skips the work as a whole.
+__device__ __forceinline__ int count_selected(bool mine) { return (int)__popcll(__ballot(mine)); }
+
+// Adds a wave's evaluated quartets to the launch's counters (one atomic from
+// one lane; the slot follows the workgroup).
+__device__ __forceinline__ void add_count(const JkArgs &a, int n) {
+    if (a.nsel && n > 0 && lane_index() == 0)
+        atomicAdd(&a.nsel[(blockIdx.x % NSEL_SLOTS) * NSEL_STRIDE], (unsigned long long)n);
 }
 
 __device__ __forceinline__ double pair_weight(int bra, int ket, const PairRec &B, const PairRec &K) {
@@ -894,17 +897,19 @@ __device__ __forceinline__ void k1_tile(const JkArgs &a, int wave) {
     const int lane = lane_index();
     {
         const int i = tile_bra(a.tile_off, a.nbra, wave);
-        const int j = (wave - a.tile_off[i]) * 64 + lane;
+        const int j0 = (wave - a.tile_off[i]) * 64, j = j0 + lane;
         const int cnt = a.bra_cnt[i];
         bool valid = j < cnt;
         const int bra = a.bra_list[i];
-        const int ket = a.ket_list[valid ? j : cnt - 1];
         const PairRec &B = a.pairs[bra];
+        if (!prefix_selectable(a, B.q, a.pairs[a.ket_list[j0]].q)) return;
+        const int ket = a.ket_list[valid ? j : cnt - 1];
         const PairRec &Kt = a.pairs[ket];
         const double wq = pair_weight(bra, ket, B, Kt);
-        bool hi;
-        screen_quartet(a, B, Kt, valid, hi);
-        if (a.sel == SEL_LOW) list_append(a, hi, bra, ket);
+        screen_quartet(a, B, Kt, valid);
+        const int n = count_selected(valid);
+        if (n == 0) return;
+        add_count(a, n);
         k1_body<LI, LJ, LK, LL, R, MODE_JK>(a, bra, ket, valid, wq, 0);
     }
 }
@@ -912,28 +917,15 @@ __device__ __forceinline__ void k1_tile(const JkArgs &a, int wave) {
 // Tiles: one wave per tile of 64 kets of one bra.
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
 __global__ void __launch_bounds__(256) jk_k1(const JkArgs a) {
-    const int lane = lane_index();
     if constexpr (MODE == MODE_JK) {
         const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
         if (wave >= a.ntiles) return;
         k1_tile<LI, LJ, LK, LL, R>(a, wave);
-    } else if constexpr (MODE == MODE_EXPORT) {
+    } else {
         const int g = blockIdx.x * 256 + threadIdx.x;
         const bool valid = g < a.nq;
         const int gg = valid ? g : a.nq - 1;
         k1_body<LI, LJ, LK, LL, R, MODE_EXPORT>(a, a.q_bra[gg], a.q_ket[gg], valid, 1.0, g);
-    } else {
-        // persistent pass over the appended list; whole waves step together
-        const int cnt = min(*a.list_count, a.nq);
-        const int stride = gridDim.x * 256;
-        for (int g0 = blockIdx.x * 256 + (threadIdx.x & ~63); g0 < cnt; g0 += stride) {
-            const int g = g0 + lane;
-            const bool valid = g < cnt;
-            const int gg = valid ? g : cnt - 1;
-            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
-            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
-            k1_body<LI, LJ, LK, LL, R, MODE_LIST>(a, bra, ket, valid, wq, 0);
-        }
     }
 }
 
@@ -974,6 +966,8 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
     const int segL = a.seg_same ? 0 : a.ncolK;
     const int per_set = (NI + NJ) * ncols + NAB;
     const PairRec B = a.pairs[bra];
+    // a task none of whose quartets can be selected ends here (uniform in the workgroup)
+    if (!prefix_selectable(a, B.q, a.pairs[a.ket_list[jbeg]].q)) return;
     // the bra's primitive pair records, then the rows
     PrimPair *sbra = reinterpret_cast<PrimPair *>(rowmem);
     double *rows = rowmem + (size_t)a.npb * (sizeof(PrimPair) / sizeof(double));
@@ -981,15 +975,19 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
     for (int t = tid; t < per_set * a.nset; t += NT) rows[t] = 0.0;
     __syncthreads();
     const int n = a.nao;
+    int evaluated = 0;  // quartets this wave evaluated (wave-uniform)
     for (int j0 = jbeg; j0 < cnt; j0 += NT) {
+        if (!prefix_selectable(a, B.q, a.pairs[a.ket_list[j0]].q)) break;  // uniform in the workgroup
         const int j = j0 + tid;
         bool valid = j < cnt;
         const int ket = a.ket_list[valid ? j : cnt - 1];
         const PairRec Kt = a.pairs[ket];
         const double wq = pair_weight(bra, ket, B, Kt);
-        bool hi;
-        screen_quartet(a, B, Kt, valid, hi);
-        if (a.sel == SEL_LOW) list_append(a, hi, bra, ket);
+        screen_quartet(a, B, Kt, valid);
+        // (no workgroup barrier inside this loop: a wave may skip a pass)
+        const int nv = count_selected(valid);
+        if (nv == 0) continue;
+        evaluated += nv;
         R V[C::NC];
         k1_compute<LI, LJ, LK, LL, R>(a, B, Kt, [&](int ib) { return sbra[ib]; }, a.npb, a.npk, V);
         const int cK = a.tpos[Kt.ish] * NK, cL = segL + a.tpos[Kt.jsh] * NL;
@@ -1101,6 +1099,7 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
             }
         }
     }
+    add_count(a, evaluated);
     __syncthreads();
     // flush nonzero entries to the global J', K'
     for (int s = 0; s < a.nset; ++s) {
@@ -1161,7 +1160,13 @@ struct K2Cfg {
     }
     static constexpr int CB = cb_();
     static constexpr int NPASS = (C::NJ + CB - 1) / CB;
-    static constexpr int TAB = C::NR * 3 * C::S;              // 2-D table entries per quartet
+    // roots whose tables are held at once: all of them where the wave's
+    // tables fit 48 KB (in FP64), otherwise blocks of RB roots one after
+    // another (the high classes of g shells)
+    static constexpr int RB = (QW * C::NR * 3 * C::S * 8 <= 48 * 1024) ? C::NR
+                              : ((48 * 1024) / (QW * 3 * C::S * 8) > 0 ? (48 * 1024) / (QW * 3 * C::S * 8) : 1);
+    static constexpr int NRB = (C::NR + RB - 1) / RB;
+    static constexpr int TAB = RB * 3 * C::S;                 // 2-D table entries per quartet
     // LDS digestion blocks: jij, jkl, kik, kil, kjk, kjl
     static constexpr int O_JIJ = 0;
     static constexpr int O_JKL = O_JIJ + C::NI * C::NJ;
@@ -1254,14 +1259,18 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
             const int ib = has ? ipq % npb : 0, ik = has ? ipq / npb : 0;
             // with a single table set per quartet the tables of pass 0 are
             // reused by the later passes
-            const bool build = pass == 0 || npq_max * nv > 1;
+            const bool build = pass == 0 || npq_max * nv > 1 || F::NRB > 1;
+#pragma unroll
+            for (int rb = 0; rb < F::NRB; ++rb) {
+            constexpr int RB = F::RB;
+            const int r0 = rb * RB, nrb = NR - r0 < RB ? NR - r0 : RB;  // roots of this block
             if (build) {
                 wave_sync();
                 const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
                 const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
                 const PQuart<R> g = prim_quartet<R>(pb, pk);
-                for (int t = sl; t < 3 * NR && lane_used; t += LPQ) {
-                    const int r = t / 3, x = t % 3;
+                for (int t = sl; t < 3 * nrb && lane_used; t += LPQ) {
+                    const int rl = t / 3, r = r0 + rl, x = t % 3;
                     R u, w;
                     rys_root1_op<NR, R>(g.T, g.rho, a.omega, var, r, a.tab, u, w);
                     const R b00 = (R)0.5 * u * g.rpq;
@@ -1277,15 +1286,16 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                     const R c00 = pax - g.fq * u * pqx;
                     const R c00p = qcx + g.fp * u * pqx;
                     const R sc2 = x == 2 ? (has ? w * g.pref : (R)0) : (R)1;
-                    R *dst = tq + (r * 3 + x) * S;
+                    R *dst = tq + (rl * 3 + x) * S;
                     rys2d<LI, LJ, LK, LL, R>(c00, c00p, b00, b10, b01, abx, cdx, sc2,
                                              [&](int ia, int ib2, int ic, int id, R v) { dst[F::tix(ia, ib2, ic, id)] = v; });
                 }
                 wave_sync();
             }
 #pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const R *tr = tq + r * 3 * S;
+            for (int rl = 0; rl < RB; ++rl) {
+                if (r0 + rl >= NR) continue;
+                const R *tr = tq + rl * 3 * S;
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
 #pragma unroll
@@ -1302,6 +1312,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                     }
                 }
             }
+            }  // root block
         }
 
         if constexpr (MODE == MODE_EXPORT) {
@@ -1432,18 +1443,20 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
 #define JK_K2_TILE(a, wave)                                                     \
     do {                                                                        \
         const int i_ = tile_bra((a).tile_off, (a).nbra, (wave));                \
-        const int j_ = ((wave) - (a).tile_off[i_]) * QW + qq;                   \
+        const int j0_ = ((wave) - (a).tile_off[i_]) * QW;                       \
+        const int j_ = j0_ + qq;                                                \
         const int cnt_ = (a).bra_cnt[i_];                                       \
         bool valid_ = lane_used && j_ < cnt_;                                   \
         const int bra_ = (a).bra_list[i_];                                      \
+        if (!prefix_selectable((a), (a).pairs[bra_].q, (a).pairs[(a).ket_list[j0_]].q)) break; \
         const int ket_ = (a).ket_list[j_ < cnt_ ? j_ : cnt_ - 1];               \
         const PairRec &B_ = (a).pairs[bra_];                                    \
         const PairRec &K_ = (a).pairs[ket_];                                    \
         const double wq_ = pair_weight(bra_, ket_, B_, K_);                     \
-        bool hi_;                                                               \
-        screen_quartet((a), B_, K_, valid_, hi_);                               \
-        if ((a).sel == SEL_LOW) list_append((a), hi_ && sl == 0, bra_, ket_);   \
-        k2_body<LI, LJ, LK, LL, R, MODE_JK>((a), tabs, dig, bra_, ket_, valid_, wq_, 0); \
+        screen_quartet((a), B_, K_, valid_);                                    \
+        const int n_ = count_selected(valid_ && sl == 0);                       \
+        add_count((a), n_);                                                     \
+        if (n_ > 0) k2_body<LI, LJ, LK, LL, R, MODE_JK>((a), tabs, dig, bra_, ket_, valid_, wq_, 0); \
     } while (0)
 
 template <int LI, int LJ, int LK, int LL, typename R, int MODE>
@@ -1459,21 +1472,11 @@ __global__ void __launch_bounds__(64) jk_k2(const JkArgs a) {
     const int qq = lane_used ? q : 0;
     if constexpr (MODE == MODE_JK) {
         JK_K2_TILE(a, (int)blockIdx.x);
-    } else if constexpr (MODE == MODE_EXPORT) {
+    } else {
         const int gq = blockIdx.x * QW + qq;
         const bool valid = lane_used && gq < a.nq;
         const int gg = gq < a.nq ? gq : a.nq - 1;
         k2_body<LI, LJ, LK, LL, R, MODE_EXPORT>(a, tabs, dig, a.q_bra[gg], a.q_ket[gg], valid, 1.0, gq);
-    } else {
-        const int cnt = min(*a.list_count, a.nq);
-        for (int b0 = blockIdx.x * QW; b0 < cnt; b0 += gridDim.x * QW) {
-            const int gq = b0 + qq;
-            const bool valid = lane_used && gq < cnt;
-            const int gg = gq < cnt ? gq : cnt - 1;
-            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
-            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
-            k2_body<LI, LJ, LK, LL, R, MODE_LIST>(a, tabs, dig, bra, ket, valid, wq, 0);
-        }
     }
 }
 
@@ -1520,6 +1523,8 @@ __global__ void __launch_bounds__(NT) jk_k2_row(const JkArgs a_in, const BatchDe
     const int i = a.row_pos[3 * task];
     const int jbeg = a.row_pos[3 * task + 1], cnt = a.row_pos[3 * task + 2];
     const int bra = a.bra_list[i];
+    // a task none of whose quartets can be selected ends here (uniform in the workgroup)
+    if (!prefix_selectable(a, a.pairs[bra].q, a.pairs[a.ket_list[jbeg]].q)) return;
     for (int t = tid; t < per_set * a.nset; t += NT) rows[t] = 0.0;
     __syncthreads();
     const int q = QW > 1 ? lane / LPQ : 0;
@@ -1527,17 +1532,22 @@ __global__ void __launch_bounds__(NT) jk_k2_row(const JkArgs a_in, const BatchDe
     const bool lane_used = q < QW;
     const int qq = lane_used ? q : 0;
     const PairRec &B = a.pairs[bra];
+    int evaluated = 0;  // quartets this wave evaluated (wave-uniform)
     for (int j0 = jbeg + wave * QW; j0 < cnt; j0 += NW * QW) {
+        if (!prefix_selectable(a, B.q, a.pairs[a.ket_list[j0]].q)) break;  // uniform in the wave
         const int j = j0 + qq;
         bool valid = lane_used && j < cnt;
         const int ket = a.ket_list[j < cnt ? j : cnt - 1];
         const PairRec &Kt = a.pairs[ket];
         const double wq = pair_weight(bra, ket, B, Kt);
-        bool hi;
-        screen_quartet(a, B, Kt, valid, hi);
-        if (a.sel == SEL_LOW) list_append(a, hi && sl == 0, bra, ket);
+        screen_quartet(a, B, Kt, valid);
+        // (no workgroup barrier inside this loop: a wave may skip a step)
+        const int nv = count_selected(valid && sl == 0);
+        if (nv == 0) continue;
+        evaluated += nv;
         k2_body<LI, LJ, LK, LL, R, MODE_JK, true>(a, tabs, dig, bra, ket, valid, wq, 0, rows, ncols, segL);
     }
+    add_count(a, evaluated);
     __syncthreads();
     const int n = a.nao;
     for (int s = 0; s < a.nset; ++s) {
@@ -1562,6 +1572,332 @@ __global__ void __launch_bounds__(NT) jk_k2_row(const JkArgs a_in, const BatchDe
     }
 }
 
+
+// ===========================================================================
+// Family 3: a lane group per quartet, one lane per Cartesian component a of
+// the bra's first shell; each lane keeps the block (a b | c d) for all b, c,
+// d in registers.  Per primitive quartet the lanes of a group first evaluate
+// the roots and weights (one lane per root) and then the vertical
+// recurrence tables G(n, m) of every root and direction (one lane per
+// table) into LDS; each lane then reads the rows n = a_x .. a_x + l_J of
+// its own component, applies the horizontal transfers on the bra and the
+// ket in registers and accumulates its elements.  Only the small G tables
+// pass through LDS, once per lane and root, instead of three table reads
+// per element and root.  Row mode only: the workgroup walks a chunk of one
+// bra's kets and keeps the bra's K rows and J_IJ in LDS (flushed once);
+// J'_KL of each quartet goes to the pair-ordered buffer.
+// ===========================================================================
+template <int LI, int LJ, int LK, int LL>
+struct K3Cfg {
+    using C = Cls<LI, LJ, LK, LL>;
+    static constexpr int NA = LI + LJ, NCC = LK + LL;
+    static constexpr int GS = (NA + 1) * (NCC + 1);   // G entries per (root, direction)
+    static constexpr int ROWS = (LJ + 1) * (NCC + 1); // G entries one lane reads per (root, direction)
+    static constexpr int LPQ = C::NI;                 // lanes per quartet
+    static constexpr int QW = 64 / LPQ;               // quartets per wave
+    static constexpr int NV = C::NJ * C::NK * C::NL;  // accumulators per lane
+    static constexpr int TS = (LJ + 1) * (LK + 1) * (LL + 1);  // per-lane table per direction
+    // per wave, in R: roots [QW][NR][2], then G [QW][NR][3][GS]
+    static constexpr int RW = QW * C::NR * 2;
+    static constexpr int GW = QW * C::NR * 3 * GS;
+    // per wave, doubles: J'_KL of the wave's quartets [QW][NK NL]
+    static constexpr int JW = QW * C::NK * C::NL;
+    template <typename R>
+    static constexpr size_t wave_bytes() { return (size_t)JW * sizeof(double) + (size_t)(RW + GW) * sizeof(R); }
+    static constexpr size_t per_set(int ncols) {
+        return sizeof(double) * ((size_t)(C::NI + C::NJ) * ncols + (size_t)C::NI * C::NJ);
+    }
+};
+
+// Vertical recurrence of one direction and root: G(n, m), n <= NA, m <= NC,
+// scaled by s, stored row-major [n][m] at dst.
+template <int NA, int NC, typename R>
+__device__ __forceinline__ void vrr2d(R c00, R c00p, R b00, R b10, R b01, R s, R *dst) {
+    R G[NA + 1][NC + 1];
+    G[0][0] = s;
+    if constexpr (NA > 0) G[1][0] = c00 * s;
+#pragma unroll
+    for (int n = 1; n < NA; ++n) G[n + 1][0] = c00 * G[n][0] + (R)n * b10 * G[n - 1][0];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+#pragma unroll
+        for (int n = 0; n <= NA; ++n) {
+            R v = c00p * G[n][m];
+            if (m > 0) v += (R)m * b01 * G[n][m - 1];
+            if (n > 0) v += (R)n * b00 * G[n - 1][m];
+            G[n][m + 1] = v;
+        }
+    }
+#pragma unroll
+    for (int n = 0; n <= NA; ++n)
+#pragma unroll
+        for (int m = 0; m <= NC; ++m) dst[n * (NC + 1) + m] = G[n][m];
+}
+
+// One lane's table T[b][c][d] (b <= LJ, c <= LK, d <= LL) of one direction
+// from the G rows n = a .. a + LJ (src, [LJ + 1][NC + 1]): horizontal
+// transfer on the bra with ab, then on the ket with cd.
+template <int LJ, int LK, int LL, typename R>
+__device__ __forceinline__ void hrr_lane(const R *src, R ab, R cd, R (&T)[(LJ + 1) * (LK + 1) * (LL + 1)]) {
+    constexpr int NC = LK + LL;
+    R X[LJ + 1][NC + 1];
+#pragma unroll
+    for (int k = 0; k <= LJ; ++k)
+#pragma unroll
+        for (int m = 0; m <= NC; ++m) X[k][m] = src[k * (NC + 1) + m];
+#pragma unroll
+    for (int b = 0; b <= LJ; ++b) {
+        if (b > 0) {
+#pragma unroll
+            for (int k = 0; k <= LJ - b; ++k)
+#pragma unroll
+                for (int m = 0; m <= NC; ++m) X[k][m] = X[k + 1][m] + ab * X[k][m];
+        }
+        R Y[NC + 1];
+#pragma unroll
+        for (int m = 0; m <= NC; ++m) Y[m] = X[0][m];
+#pragma unroll
+        for (int d = 0; d <= LL; ++d) {
+            if (d > 0) {
+#pragma unroll
+                for (int c = 0; c <= NC - d; ++c) Y[c] = Y[c + 1] + cd * Y[c];
+            }
+#pragma unroll
+            for (int c = 0; c <= LK; ++c) T[(b * (LK + 1) + c) * (LL + 1) + d] = Y[c];
+        }
+    }
+}
+
+template <int LI, int LJ, int LK, int LL, typename R, int NT, bool BATCH>
+__global__ void __launch_bounds__(NT) jk_k3_row(const JkArgs a_in, const BatchDesc *__restrict__ descs, int ndesc) {
+    using C = Cls<LI, LJ, LK, LL>;
+    using F = K3Cfg<LI, LJ, LK, LL>;
+    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, NAB = C::NAB;
+    constexpr int LPQ = F::LPQ, QW = F::QW, NW = NT / 64, NCC = F::NCC, TS = F::TS;
+    extern __shared__ double smem3[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = lane_index();
+    int task = blockIdx.x;
+    JkArgs a = a_in;
+    if constexpr (BATCH) {
+        const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, task));
+        a = descs[m].a;
+        task -= descs[m].tile_base;
+    }
+    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
+    const int segL = a.seg_same ? 0 : a.ncolK;
+    const int per_set = (NI + NJ) * ncols + NAB;
+    double *rows = smem3;
+    double *jkl = rows + (size_t)per_set * a.nset + (size_t)wave * F::JW;
+    R *rt = (R *)(rows + (size_t)per_set * a.nset + (size_t)NW * F::JW) + (size_t)wave * (F::RW + F::GW);
+    R *gt = rt + F::RW;
+    const int i = a.row_pos[3 * task];
+    const int jbeg = a.row_pos[3 * task + 1], cnt = a.row_pos[3 * task + 2];
+    const int bra = a.bra_list[i];
+    // a task none of whose quartets can be selected ends here (uniform in the workgroup)
+    if (!prefix_selectable(a, a.pairs[bra].q, a.pairs[a.ket_list[jbeg]].q)) return;
+    for (int t = tid; t < per_set * a.nset; t += NT) rows[t] = 0.0;
+    for (int t = lane; t < F::JW; t += 64) jkl[t] = 0.0;
+    __syncthreads();
+    const int q = lane / LPQ, ia = lane % LPQ;
+    const bool lane_used = q < QW;
+    const int qq = lane_used ? q : 0;
+    // Cartesian exponents of this lane's bra component
+    int ae[3] = {0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < NI; ++t)
+        if (t == ia) { ae[0] = cart_comp(LI, t, 0); ae[1] = cart_comp(LI, t, 1); ae[2] = cart_comp(LI, t, 2); }
+    const PairRec B = a.pairs[bra];
+    const R ab[3] = {(R)B.ab[0], (R)B.ab[1], (R)B.ab[2]};
+    const int n = a.nao;
+    int evaluated = 0;  // quartets this wave evaluated (wave-uniform)
+    for (int j0 = jbeg + wave * QW; j0 < cnt; j0 += NW * QW) {
+        if (!prefix_selectable(a, B.q, a.pairs[a.ket_list[j0]].q)) break;  // uniform in the wave
+        const int j = j0 + qq;
+        bool valid = lane_used && j < cnt;
+        const int ket = a.ket_list[j < cnt ? j : cnt - 1];
+        const PairRec Kt = a.pairs[ket];
+        const double wq = pair_weight(bra, ket, B, Kt);
+        screen_quartet(a, B, Kt, valid);
+        // (no workgroup barrier inside this loop: a wave may skip a step)
+        const int nv = count_selected(valid && ia == 0);
+        if (nv == 0) continue;
+        evaluated += nv;
+        const R cd[3] = {(R)Kt.ab[0], (R)Kt.ab[1], (R)Kt.ab[2]};
+        R V[F::NV];
+#pragma unroll
+        for (int e = 0; e < F::NV; ++e) V[e] = (R)0;
+        const int vb = variant_begin(a.omega), nvar = variant_end(a.omega) - vb;
+        for (int ik = 0; ik < a.npk; ++ik) {
+            const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
+            for (int ib = 0; ib < a.npb; ++ib) {
+                const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
+                const PQuart<R> g = prim_quartet<R>(pb, pk);
+                for (int var = vb; var < vb + nvar; ++var) {
+                    R *rq = rt + qq * (NR * 2);
+                    R *gq = gt + qq * (NR * 3 * F::GS);
+                    wave_sync();
+                    // roots and weights, one lane per root
+                    if (lane_used && ia < NR) {
+                        R u, w;
+                        rys_root1_op<NR, R>(g.T, g.rho, a.omega, var, ia, a.tab, u, w);
+                        rq[2 * ia] = u;
+                        rq[2 * ia + 1] = w * g.pref;
+                    }
+                    wave_sync();
+                    // vertical recurrence tables, one lane per (root, direction)
+                    for (int t = ia; t < 3 * NR && lane_used; t += LPQ) {
+                        const int r = t / 3, x = t % 3;
+                        const R u = rq[2 * r];
+                        const R b00 = (R)0.5 * u * g.rpq;
+                        const R b10 = g.hb * ((R)1 - g.fq * u);
+                        const R b01 = g.hk * ((R)1 - g.fp * u);
+                        const R pqx = sel3(x, g.PQ[0], g.PQ[1], g.PQ[2]);
+                        const R pax = sel3(x, g.PA[0], g.PA[1], g.PA[2]);
+                        const R qcx = sel3(x, g.QC[0], g.QC[1], g.QC[2]);
+                        const R c00 = pax - g.fq * u * pqx;
+                        const R c00p = qcx + g.fp * u * pqx;
+                        const R s = x == 2 ? rq[2 * r + 1] : (R)1;
+                        vrr2d<F::NA, NCC, R>(c00, c00p, b00, b10, b01, s, gq + (r * 3 + x) * F::GS);
+                    }
+                    wave_sync();
+                    // this lane's rows, transfers and elements, root by root
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        R T[3][TS];
+#pragma unroll
+                        for (int x = 0; x < 3; ++x)
+                            hrr_lane<LJ, LK, LL, R>(gq + (r * 3 + x) * F::GS + ae[x] * (NCC + 1), ab[x], cd[x], T[x]);
+#pragma unroll
+                        for (int b = 0; b < NJ; ++b)
+#pragma unroll
+                            for (int c = 0; c < NK; ++c)
+#pragma unroll
+                                for (int d = 0; d < NL; ++d) {
+                                    const int ix = (cart_comp(LJ, b, 0) * (LK + 1) + cart_comp(LK, c, 0)) * (LL + 1) + cart_comp(LL, d, 0);
+                                    const int iy = (cart_comp(LJ, b, 1) * (LK + 1) + cart_comp(LK, c, 1)) * (LL + 1) + cart_comp(LL, d, 1);
+                                    const int iz = (cart_comp(LJ, b, 2) * (LK + 1) + cart_comp(LK, c, 2)) * (LL + 1) + cart_comp(LL, d, 2);
+                                    V[(b * NK + c) * NL + d] += T[0][ix] * T[1][iy] * T[2][iz];
+                                }
+                    }
+                }
+            }
+        }
+        // digestion of this lane's elements (a b | c d), b, c, d all
+        const int cK = a.tpos[Kt.ish] * NK, cL = segL + a.tpos[Kt.jsh] * NL;
+        const int ga = B.aoi + ia;
+        for (int s = 0; s < a.nset; ++s) {
+            const double *D = a.D + s * a.mstride;
+            double *rm = rows + s * per_set;
+            double *rI = rm, *rJ = rm + NI * ncols, *rjij = rm + (NI + NJ) * ncols;
+            if (valid) {
+                if (a.do_j) {
+                    double dab[NJ], jab[NJ];
+#pragma unroll
+                    for (int b = 0; b < NJ; ++b) {
+                        dab[b] = D[ga * n + B.aoj + b];
+                        jab[b] = 0.0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < NK; ++c)
+#pragma unroll
+                        for (int d = 0; d < NL; ++d) {
+                            const double dcd = D[(Kt.aoi + c) * n + Kt.aoj + d];
+                            double p = 0.0;
+#pragma unroll
+                            for (int b = 0; b < NJ; ++b) {
+                                const double v = (double)V[(b * NK + c) * NL + d];
+                                jab[b] += v * dcd;
+                                p += v * dab[b];
+                            }
+                            atomicAdd(&jkl[qq * (NK * NL) + c * NL + d], 2.0 * wq * p);
+                        }
+#pragma unroll
+                    for (int b = 0; b < NJ; ++b) atomicAdd(&rjij[ia * NJ + b], 2.0 * wq * jab[b]);
+                }
+                if (a.do_k) {
+                    double dac[NK], dad[NL];
+#pragma unroll
+                    for (int c = 0; c < NK; ++c) dac[c] = D[ga * n + Kt.aoi + c];
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) dad[d] = D[ga * n + Kt.aoj + d];
+                    double kac[NK], kad[NL];
+#pragma unroll
+                    for (int c = 0; c < NK; ++c) kac[c] = 0.0;
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) kad[d] = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NJ; ++b) {
+                        const int gb = B.aoj + b;
+                        double kbc[NK], kbd[NL];
+#pragma unroll
+                        for (int c = 0; c < NK; ++c) kbc[c] = 0.0;
+#pragma unroll
+                        for (int d = 0; d < NL; ++d) kbd[d] = 0.0;
+#pragma unroll
+                        for (int c = 0; c < NK; ++c) {
+                            const double dbc = D[gb * n + Kt.aoi + c];
+#pragma unroll
+                            for (int d = 0; d < NL; ++d) {
+                                const double v = (double)V[(b * NK + c) * NL + d];
+                                const double dbd = D[gb * n + Kt.aoj + d];
+                                kac[c] += v * dbd;
+                                kad[d] += v * dbc;
+                                kbc[c] += v * dad[d];
+                                kbd[d] += v * dac[c];
+                            }
+                        }
+#pragma unroll
+                        for (int c = 0; c < NK; ++c) atomicAdd(&rJ[b * ncols + cK + c], wq * kbc[c]);
+#pragma unroll
+                        for (int d = 0; d < NL; ++d) atomicAdd(&rJ[b * ncols + cL + d], wq * kbd[d]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < NK; ++c) atomicAdd(&rI[ia * ncols + cK + c], wq * kac[c]);
+#pragma unroll
+                    for (int d = 0; d < NL; ++d) atomicAdd(&rI[ia * ncols + cL + d], wq * kad[d]);
+                }
+            }
+            if (a.do_j) {
+                // J'_KL of the wave's quartets into the pair-ordered buffer
+                wave_sync();
+                for (int t = lane; t < QW * NK * NL; t += 64) {
+                    const int q2 = t / (NK * NL), e = t % (NK * NL);
+                    const double v = jkl[t];
+                    jkl[t] = 0.0;
+                    const int j2 = j0 + q2;
+                    if (j2 < cnt && v != 0.0) {
+                        const PairRec &K2 = a.pairs[a.ket_list[j2]];
+                        atomic_add_f64(&a.jp[s * a.jpstride + K2.jp_off + (int64_t)e * K2.pp_stride], v);
+                    }
+                }
+                wave_sync();
+            }
+        }
+    }
+    add_count(a, evaluated);
+    __syncthreads();
+    // flush nonzero entries to the global J', K'
+    for (int s = 0; s < a.nset; ++s) {
+        const double *rm = rows + s * per_set;
+        double *Jm = a.J + s * a.mstride;
+        double *Km = a.K + s * a.mstride;
+        for (int t = tid; t < per_set; t += NT) {
+            const double v = rm[t];
+            if (v == 0.0) continue;
+            if (t >= (NI + NJ) * ncols) {
+                const int e = t - (NI + NJ) * ncols;
+                atomic_add_f64(&Jm[(B.aoi + e / NJ) * n + B.aoj + e % NJ], v);
+                continue;
+            }
+            const int r = t / ncols, c = t % ncols;
+            const int row = r < NI ? B.aoi + r : B.aoj + (r - NI);
+            int col;
+            if (c < a.ncolK) col = a.aoc[a.tshK[c / NK]] + c % NK;
+            else col = a.aoc[a.tshL[(c - a.ncolK) / NL]] + (c - a.ncolK) % NL;
+            atomic_add_f64(&Km[row * n + col], v);
+        }
+    }
+}
 
 // ===========================================================================
 // Batched builds: one launch per (class, family) covers the tiles of every
@@ -1594,50 +1930,6 @@ __global__ void __launch_bounds__(64) jk_k2_batch(const BatchDesc *__restrict__ 
     const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
     const JkArgs a = descs[m].a;
     JK_K2_TILE(a, g - descs[m].tile_base);
-}
-
-// FP64 pass of the mixed split over every descriptor's appended list.
-template <int LI, int LJ, int LK, int LL>
-__global__ void __launch_bounds__(256) jk_k1_batch_list(const BatchDesc *__restrict__ descs, int ndesc) {
-    const int lane = lane_index();
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), nwave = gridDim.x * 4;
-    for (int m = 0; m < ndesc; ++m) {
-        const JkArgs &a = descs[m].a;
-        const int cnt = min(*a.list_count, a.nq);
-        for (int g0 = wave * 64; g0 < cnt; g0 += nwave * 64) {
-            const int g = g0 + lane;
-            const bool valid = g < cnt;
-            const int gg = valid ? g : cnt - 1;
-            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
-            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
-            k1_body<LI, LJ, LK, LL, double, MODE_LIST>(a, bra, ket, valid, wq, 0);
-        }
-    }
-}
-
-template <int LI, int LJ, int LK, int LL>
-__global__ void __launch_bounds__(64) jk_k2_batch_list(const BatchDesc *__restrict__ descs, int ndesc) {
-    using F = K2Cfg<LI, LJ, LK, LL>;
-    constexpr int QW = F::QW, LPQ = F::LPQ;
-    __shared__ double tabs[QW * F::TAB];
-    __shared__ double dig[F::DIGW];
-    const int lane = lane_index();
-    const int q = QW > 1 ? lane / LPQ : 0;
-    const bool lane_used = q < QW;
-    const int qq = lane_used ? q : 0;
-    for (int m = 0; m < ndesc; ++m) {
-        const JkArgs &a = descs[m].a;
-        const int cnt = min(*a.list_count, a.nq);
-        for (int b0 = blockIdx.x * QW; b0 < cnt; b0 += gridDim.x * QW) {
-            const int gq = b0 + qq;
-            const bool valid = lane_used && gq < cnt;
-            const int gg = gq < cnt ? gq : cnt - 1;
-            const int bra = a.list[2 * gg], ket = a.list[2 * gg + 1];
-            const double wq = pair_weight(bra, ket, a.pairs[bra], a.pairs[ket]);
-            wave_sync();
-            k2_body<LI, LJ, LK, LL, double, MODE_LIST>(a, tabs, dig, bra, ket, valid, wq, 0);
-        }
-    }
 }
 
 }  // namespace jk

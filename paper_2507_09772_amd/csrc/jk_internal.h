@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -112,7 +113,7 @@ __device__ __forceinline__ double finalize_elem(const AoMaps &m, const double *X
 }
 
 // Entry t = (I, J) of max_s max_{a in I, b in J} |Dc[s][a][b]|.
-__device__ __forceinline__ float dmax_elem(const double *Dc, const int32_t *aoc, const int32_t *l, int ns, int naoc,
+__device__ __forceinline__ double dmax_elem(const double *Dc, const int32_t *aoc, const int32_t *l, int ns, int naoc,
                                            int nset, int t) {
     const int I = t / ns, J = t % ns;
     double m = 0.0;
@@ -120,7 +121,7 @@ __device__ __forceinline__ float dmax_elem(const double *Dc, const int32_t *aoc,
         for (int a = 0; a < ncart(l[I]); ++a)
             for (int b = 0; b < ncart(l[J]); ++b)
                 m = fmax(m, fabs(Dc[(int64_t)s * naoc * naoc + (int64_t)(aoc[I] + a) * naoc + aoc[J] + b]));
-    return (float)m;
+    return m;
 }
 
 struct DevBuf {
@@ -135,9 +136,9 @@ struct ClassTask {
     // row mode: long bras (positions into d_bra / d_cnt) and the short rest
     int nrow = 0, nsbra = 0, nstiles[2] = {0, 0};
     int64_t nq_row = 0;  // quartets of the long bras
-    int nrowc[2] = {0, 0};                       // row tasks per family
-    int32_t *d_rowc[2] = {nullptr, nullptr};     // (list position, ket begin, ket end) per task
-    std::vector<int32_t> h_rowc[2];              // host copies (batched builds)
+    int nrowc[3] = {0, 0, 0};                    // row tasks per family
+    int32_t *d_rowc[3] = {nullptr, nullptr, nullptr};  // (list position, ket begin, ket end) per task
+    std::vector<int32_t> h_rowc[3];              // host copies (batched builds)
     int nsrow = 0;                               // short bras as 64-lane row tasks
     int32_t *d_srowt = nullptr;
     std::vector<int32_t> h_srowt;
@@ -148,7 +149,7 @@ struct ClassTask {
     bool row_ok[2];      // row mode allowed per precision
     bool row_short[2];   // short bras in row mode too (64-lane workgroups)
     int ntiles[2];       // per family - 1
-    int64_t nq, npq, list_off;
+    int64_t nq, npq;
     double flops;
     int32_t *d_bra = nullptr, *d_cnt = nullptr, *d_tile[2] = {nullptr, nullptr};
     const int32_t *d_ket = nullptr;
@@ -171,12 +172,16 @@ struct jk_plan {
     int scratch_nset = 0, dc_nset = 0;
     double *d_jp = nullptr;  // pair-ordered J'_KL buffer [scratch_nset][njp]
     int64_t njp = 0;
-    int32_t *d_list = nullptr, *d_list_cnt = nullptr;  // mixed split
+    // quartets evaluated per launch of the last build: [class][precision][kind]
+    // counted on the device (NSEL_SLOTS counters each), or known on the host
+    unsigned long long *d_nsel = nullptr;
+    const unsigned long long *last_nsel = nullptr;  // device counters of the last build
+    std::vector<int64_t> last_fixed;                 // host count per launch, -1: on the device
+    int last_precision = -1;
     int32_t *d_tpos = nullptr;                         // shell -> index within its type
-    bool last_mixed = false;
     double dscreen = 0.0;  // density screening threshold for later builds (0: off)
     bool no_row = false;  // JK_NO_ROW=1 in the environment: tiles only (A/B measurements)
-    float *d_dmax = nullptr;
+    double *d_dmax = nullptr;
     Tables tab{};
     jk_stats stats{};
     int device = 0;
@@ -205,3 +210,31 @@ struct jk_plan {
         for (void *p : allocs) (void)hipFree(p);
     }
 };
+
+// Device scratch of one build: Cartesian J', K' and density, the pair-ordered
+// J'_KL buffer, the density block maxima and the per-launch counters.
+struct Scratch {
+    double *Jc, *Kc, *Dc, *jp, *dmax;
+    unsigned long long *nsel;
+};
+
+// Elements of each scratch array for a build with nset densities.
+struct ScratchSizes {
+    size_t mat, jp, dc, dmax, nsel;
+};
+inline ScratchSizes scratch_sizes(const jk_plan *P, int nset) {
+    ScratchSizes z;
+    z.mat = (size_t)nset * P->naoc * P->naoc;
+    z.jp = (size_t)nset * P->njp;
+    z.dc = P->sph ? z.mat : 0;
+    z.dmax = (size_t)P->ns * P->ns + 1;  // the table and its largest entry
+    z.nsel = 8 * std::max<size_t>(P->cls.size(), 1) * NSEL_SLOTS * NSEL_STRIDE;
+    return z;
+}
+
+// Argument checks shared by the build entry points (0 or a JK_E* code).
+int check_execute_args(const jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision,
+                       double mix_threshold, double omega, double *J, double *K);
+// One J/K build into the given scratch (arguments already checked).
+int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision, double mix_threshold,
+                 double omega, double *J, double *K, hipStream_t s, const Scratch &sc, bool allow_profile);

@@ -11,19 +11,16 @@ constexpr int LMAX_BUILT = 3;  // classes instantiated up to (ff|ff)
 using Launcher = hipError_t (*)(const JkArgs &, hipStream_t);
 // Batched builds: the tiles of many descriptors (molecules) in one launch.
 using BatchLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int total_tiles, hipStream_t);
-using BatchListLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int64_t nq_total, hipStream_t);
 using BatchRowLauncher = hipError_t (*)(const BatchDesc *, int ndesc, int total_tasks, size_t lds, hipStream_t);
 
 struct ClassEntry {
-    Launcher tiles[2][2];  // [family - 1][0: FP64, 1: FP32], quartets from tiles
-    Launcher list64[2];    // [family - 1], FP64 pass over the appended list
+    Launcher tiles[3][2];  // [family - 1][0: FP64, 1: FP32], quartets from tiles (none for family 3)
     Launcher ex64, ex32;   // export (default family)
-    Launcher row[2][2];    // row mode, 256-lane workgroups (long bras), [family - 1][0: FP64, 1: FP32]
-    Launcher srow[2][2];   // row mode, 64-lane workgroups (short bras)
-    size_t row_fixed[2][2];  // row-mode LDS bytes per wave besides the K rows, [family - 1][precision]
-    BatchLauncher batch[2][2];       // [family - 1][precision]
-    BatchListLauncher batch_list[2]; // [family - 1], FP64 list pass of the mixed split
-    BatchRowLauncher batch_row[2][2];  // 64-lane row tasks of many descriptors
+    Launcher row[3][2];    // row mode, 256-lane workgroups (long bras), [family - 1][0: FP64, 1: FP32]
+    Launcher srow[3][2];   // row mode, 64-lane workgroups (short bras)
+    size_t row_fixed[3][2];  // row-mode LDS bytes per wave besides the K rows, [family - 1][precision]
+    BatchLauncher batch[3][2];       // [family - 1][precision]
+    BatchRowLauncher batch_row[3][2];  // 64-lane row tasks of many descriptors
 };
 
 // LDS bytes of one row-mode workgroup of nw waves: the fixed part (per wave;
@@ -34,12 +31,6 @@ inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj
     return (size_t)nw * e.row_fixed[fam - 1][pr] + (fam == 1 ? sizeof(PrimPair) * (size_t)npb : 0) +
            sizeof(double) * (size_t)nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj));
 }
-
-// Classes whose quartets the mixed precision mode splits into FP32 and FP64
-// (the rest it computes in FP64): on this chip single-precision vector
-// arithmetic runs at the FP64 rate, so only the one-root classes, bound by
-// their Boys-table gathers (20 bytes per lane in FP32 against 64), gain.
-inline bool mixed_split_class(int li, int lj, int lk, int ll) { return nroots(li, lj, lk, ll) == 1; }
 
 // LDS budget of one row-mode workgroup (dynamic shared memory; gfx950 has
 // 160 KB per CU, kernels above 64 KB opt in through a function attribute).

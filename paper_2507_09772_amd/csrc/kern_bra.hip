@@ -14,8 +14,7 @@ template <int LI, int LJ, int LK, int LL, typename R, int MODE>
 static hipError_t launch_k1(const JkArgs &a, hipStream_t s) {
     int grid;
     if constexpr (MODE == MODE_JK) grid = (a.ntiles + 3) / 4;
-    else if constexpr (MODE == MODE_EXPORT) grid = (a.nq + 255) / 256;
-    else grid = std::min((a.nq + 255) / 256, 2048);
+    else grid = (a.nq + 255) / 256;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((jk_k1<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -64,6 +63,32 @@ static hipError_t launch_row2(const JkArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int LI, int LJ, int LK, int LL, typename R, int NT>
+static hipError_t launch_row3(const JkArgs &a, hipStream_t s) {
+    if (a.nrow <= 0) return hipSuccess;
+    using F = K3Cfg<LI, LJ, LK, LL>;
+    const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
+    const size_t lds = (NT / 64) * F::template wave_bytes<R>() + (size_t)a.nset * F::per_set(ncols);
+    if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
+    static bool opted_in = false;
+    const hipError_t e = lds_opt_in(&jk_k3_row<LI, LJ, LK, LL, R, NT, false>, lds, opted_in);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((jk_k3_row<LI, LJ, LK, LL, R, NT, false>), dim3(a.nrow), dim3(NT), lds, s, a,
+                       (const BatchDesc *)nullptr, 0);
+    return hipGetLastError();
+}
+
+template <int LI, int LJ, int LK, int LL, typename R>
+static hipError_t launch_row3_batch(const BatchDesc *d, int ndesc, int total, size_t lds, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if (lds > (size_t)ROW_LDS_MAX) return hipErrorInvalidValue;
+    static bool opted_in = false;
+    const hipError_t e = lds_opt_in(&jk_k3_row<LI, LJ, LK, LL, R, 64, true>, lds, opted_in);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((jk_k3_row<LI, LJ, LK, LL, R, 64, true>), dim3(total), dim3(64), lds, s, JkArgs{}, d, ndesc);
+    return hipGetLastError();
+}
+
 // Batched 64-lane row tasks; lds = the largest workgroup need over the descriptors.
 template <int LI, int LJ, int LK, int LL, typename R>
 static hipError_t launch_row_batch(const BatchDesc *d, int ndesc, int total, size_t lds, hipStream_t s) {
@@ -92,8 +117,7 @@ static hipError_t launch_k2(const JkArgs &a, hipStream_t s) {
     constexpr int QW = k2_qw(LI, LJ, LK, LL);
     int grid;
     if constexpr (MODE == MODE_JK) grid = a.ntiles;
-    else if constexpr (MODE == MODE_EXPORT) grid = (a.nq + QW - 1) / QW;
-    else grid = std::min((a.nq + QW - 1) / QW, 8192);
+    else grid = (a.nq + QW - 1) / QW;
     if (grid <= 0) return hipSuccess;
     hipLaunchKernelGGL((jk_k2<LI, LJ, LK, LL, R, MODE>), dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError();
@@ -114,23 +138,6 @@ static hipError_t launch_k2_batch(const BatchDesc *d, int ndesc, int total, hipS
     return hipGetLastError();
 }
 
-template <int LI, int LJ, int LK, int LL>
-static hipError_t launch_k1_batch_list(const BatchDesc *d, int ndesc, int64_t nq, hipStream_t s) {
-    if (ndesc <= 0 || nq <= 0) return hipSuccess;
-    const int grid = (int)std::min<int64_t>((nq + 255) / 256, 1024);
-    hipLaunchKernelGGL((jk_k1_batch_list<LI, LJ, LK, LL>), dim3(grid), dim3(256), 0, s, d, ndesc);
-    return hipGetLastError();
-}
-
-template <int LI, int LJ, int LK, int LL>
-static hipError_t launch_k2_batch_list(const BatchDesc *d, int ndesc, int64_t nq, hipStream_t s) {
-    if (ndesc <= 0 || nq <= 0) return hipSuccess;
-    constexpr int QW = k2_qw(LI, LJ, LK, LL);
-    const int grid = (int)std::min<int64_t>((nq + QW - 1) / QW, 4096);
-    hipLaunchKernelGGL((jk_k2_batch_list<LI, LJ, LK, LL>), dim3(grid), dim3(64), 0, s, d, ndesc);
-    return hipGetLastError();
-}
-
 template <int LK, int LL>
 static void reg_one() {
     constexpr int LI = JK_LI, LJ = JK_LJ;
@@ -139,7 +146,6 @@ static void reg_one() {
         if constexpr (has_family1(LI, LJ, LK, LL)) {
             e.tiles[0][0] = &launch_k1<LI, LJ, LK, LL, double, MODE_JK>;
             e.tiles[0][1] = &launch_k1<LI, LJ, LK, LL, float, MODE_JK>;
-            e.list64[0] = &launch_k1<LI, LJ, LK, LL, double, MODE_LIST>;
             e.row[0][0] = &launch_row<LI, LJ, LK, LL, double, 256>;
             e.row[0][1] = &launch_row<LI, LJ, LK, LL, float, 256>;
             e.srow[0][0] = &launch_row<LI, LJ, LK, LL, double, 64>;
@@ -148,12 +154,10 @@ static void reg_one() {
             e.batch_row[0][1] = &launch_row_batch<LI, LJ, LK, LL, float>;
             e.batch[0][0] = &launch_k1_batch<LI, LJ, LK, LL, double>;
             e.batch[0][1] = &launch_k1_batch<LI, LJ, LK, LL, float>;
-            e.batch_list[0] = &launch_k1_batch_list<LI, LJ, LK, LL>;
         }
         if constexpr (has_family2(LI, LJ, LK, LL)) {
             e.tiles[1][0] = &launch_k2<LI, LJ, LK, LL, double, MODE_JK>;
             e.tiles[1][1] = &launch_k2<LI, LJ, LK, LL, float, MODE_JK>;
-            e.list64[1] = &launch_k2<LI, LJ, LK, LL, double, MODE_LIST>;
             e.row[1][0] = &launch_row2<LI, LJ, LK, LL, double, 256>;
             e.row[1][1] = &launch_row2<LI, LJ, LK, LL, float, 256>;
             e.srow[1][0] = &launch_row2<LI, LJ, LK, LL, double, 64>;
@@ -164,7 +168,16 @@ static void reg_one() {
             e.row_fixed[1][1] = K2RowLds<LI, LJ, LK, LL>::template fixed<float>();
             e.batch[1][0] = &launch_k2_batch<LI, LJ, LK, LL, double>;
             e.batch[1][1] = &launch_k2_batch<LI, LJ, LK, LL, float>;
-            e.batch_list[1] = &launch_k2_batch_list<LI, LJ, LK, LL>;
+        }
+        if constexpr (has_family3(LI, LJ, LK, LL)) {
+            e.row[2][0] = &launch_row3<LI, LJ, LK, LL, double, 256>;
+            e.row[2][1] = &launch_row3<LI, LJ, LK, LL, float, 256>;
+            e.srow[2][0] = &launch_row3<LI, LJ, LK, LL, double, 64>;
+            e.srow[2][1] = &launch_row3<LI, LJ, LK, LL, float, 64>;
+            e.batch_row[2][0] = &launch_row3_batch<LI, LJ, LK, LL, double>;
+            e.batch_row[2][1] = &launch_row3_batch<LI, LJ, LK, LL, float>;
+            e.row_fixed[2][0] = K3Cfg<LI, LJ, LK, LL>::template wave_bytes<double>();
+            e.row_fixed[2][1] = K3Cfg<LI, LJ, LK, LL>::template wave_bytes<float>();
         }
         if constexpr (default_family(LI, LJ, LK, LL) == 1) {
             e.ex64 = &launch_k1<LI, LJ, LK, LL, double, MODE_EXPORT>;
@@ -181,6 +194,7 @@ static int reg_all() {
     reg_one<1, 0>(); reg_one<1, 1>();
     reg_one<2, 0>(); reg_one<2, 1>(); reg_one<2, 2>();
     reg_one<3, 0>(); reg_one<3, 1>(); reg_one<3, 2>(); reg_one<3, 3>();
+    reg_one<4, 0>(); reg_one<4, 1>(); reg_one<4, 2>(); reg_one<4, 3>(); reg_one<4, 4>();
     return 0;
 }
 

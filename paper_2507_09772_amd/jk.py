@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libjk.so")
 
 JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE = 0, -1, -2, -3, -4
 JK_FP64, JK_MIXED, JK_FP32 = 0, 1, 2
-JK_DO_J, JK_DO_K, JK_ACCUMULATE = 1, 2, 4
+JK_DO_J, JK_DO_K, JK_ACCUMULATE, JK_CHECK_SYMMETRY = 1, 2, 4, 8
 PRECISION = {"fp64": JK_FP64, "mixed": JK_MIXED, "fp32": JK_FP32}
 
 
@@ -35,7 +35,8 @@ class _Basis(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("nquartets", ctypes.c_int64), ("nprim_quartets", ctypes.c_int64),
                 ("nquartets_fp32", ctypes.c_int64), ("nclasses", ctypes.c_int32),
-                ("npairs", ctypes.c_int32), ("setup_ms", ctypes.c_double), ("model_flops", ctypes.c_double)]
+                ("npairs", ctypes.c_int32), ("setup_ms", ctypes.c_double), ("model_flops", ctypes.c_double),
+                ("nquartets_evaluated", ctypes.c_int64)]
 
 
 class ClassTiming(ctypes.Structure):
@@ -68,6 +69,7 @@ def lib():
         L.jk_boys_eval.argtypes = [i32, vp, i32, i32, vp]
         L.jk_batch_create.argtypes = [vp, i32, i32, i32, f64, ctypes.POINTER(vp)]
         L.jk_batch_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.jk_batch_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.jk_batch_destroy.argtypes = [vp]
         L.jk_batch_destroy.restype = None
         L.jk_plan_profile.argtypes = [vp, i32]
@@ -77,6 +79,7 @@ def lib():
         L.jk_tune_get.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.jk_tune_load.argtypes = [ctypes.c_char_p]
         L.jk_tune_set_row.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.jk_tune_set_shape.argtypes = [i32, i32, i32, i32, i32, i32]
         L.jk_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -234,6 +237,12 @@ class Batch:
         ptrs = [(ctypes.c_void_p * n)(*[M.data_ptr() for M in Ms]) for Ms in (Ds, Js, Ks)]
         _check(lib().jk_batch_execute(self.h, ptrs[0], ptrs[1], ptrs[2], _stream_handle(stream)))
 
+    def stats(self):
+        """(quartets the last execute evaluated, how many of them in FP32)."""
+        n, n32 = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().jk_batch_stats(self.h, ctypes.byref(n), ctypes.byref(n32)))
+        return n.value, n32.value
+
 
 def build(mol, D, cutoff=1e-13, precision="fp64", stream=None):
     """One-shot jk_build.  D: torch float64 CUDA [nset, nao, nao]."""
@@ -249,7 +258,7 @@ def build(mol, D, cutoff=1e-13, precision="fp64", stream=None):
 
 
 def tune_set(li, lj, lk, ll, precision, family):
-    """Kernel family (1, 2; 0 = default) for one canonical class."""
+    """Kernel family (1, 2, 3; 0 = default) for one canonical class."""
     _check(lib().jk_tune_set(li, lj, lk, ll, PRECISION[precision], family))
 
 
@@ -260,8 +269,15 @@ def tune_set_row(li, lj, lk, ll, precision, row):
     _check(lib().jk_tune_set_row(li, lj, lk, ll, PRECISION[precision], row))
 
 
+def tune_set_shape(li, lj, lk, ll, min_kets=0, chunk=0):
+    """Task shape of one canonical class: long-bra threshold and kets per row
+    task (0 = default)."""
+    _check(lib().jk_tune_set_shape(li, lj, lk, ll, min_kets, chunk))
+
+
 def tune_get(li, lj, lk, ll, precision):
-    """(family a new plan would use, bit mask of built families)."""
+    """(family a new plan would use, bit mask of built families: 1, 2, 4 for
+    families 1, 2, 3)."""
     f, m = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().jk_tune_get(li, lj, lk, ll, PRECISION[precision], ctypes.byref(f), ctypes.byref(m)))
     return f.value, m.value

@@ -24,7 +24,9 @@ Workloads (the shapes and value distributions of the paper's benchmarks,
 Section 4, with synthetic water lattices standing in for its molecules):
 
 * basis A: split-valence + polarisation, Cartesian (6-31G*-shaped);
-* basis B: triple-zeta + double polarisation, spherical (def2-TZVPP-shaped).
+* basis B: triple-zeta + double polarisation, spherical (def2-TZVPP-shaped);
+* basis C: quadruple-zeta with g shells, spherical (cc-pVQZ-shaped:
+  O [5s4p3d2f1g], H [4s3p2d1f]).
 """
 from __future__ import annotations
 
@@ -45,7 +47,14 @@ BASIS_B_SHELLS = {
           (1, 4, False), (1, 1, False), (1, 1, False), (2, 1, False), (2, 1, False), (3, 1, False)],
     "H": [(0, 3, False), (0, 1, False), (0, 1, False), (1, 1, False)],
 }
-BASIS_SEED = {"A": 101, "B": 102}
+BASIS_C_SHELLS = {
+    "O": [(0, 6, True), (0, 2, False), (0, 1, False), (0, 1, False), (0, 1, False),
+          (1, 4, False), (1, 1, False), (1, 1, False), (1, 1, False),
+          (2, 1, False), (2, 1, False), (2, 1, False), (3, 1, False), (3, 1, False), (4, 1, False)],
+    "H": [(0, 3, False), (0, 1, False), (0, 1, False), (0, 1, False),
+          (1, 1, False), (1, 1, False), (1, 1, False), (2, 1, False), (2, 1, False), (3, 1, False)],
+}
+BASIS_SEED = {"A": 101, "B": 102, "C": 103}
 CORE_RANGE = (0.1, 5.0e3)
 VALENCE_RANGE = (0.1, 10.0)
 
@@ -98,14 +107,14 @@ class BasisTemplate:
 
 
 def make_basis(name: str) -> BasisTemplate:
-    """Draw basis A or B from its fixed seed.
+    """Draw basis A, B or C from its fixed seed.
 
     Exponents: log-uniform on [0.1, 5e3] for the core shell and on [0.1, 10]
     for every other shell, sorted descending.  Raw contraction weights
     U(0.2, 1) (1 for single-primitive shells), then normalised as described
     in the module docstring.
     """
-    spec = {"A": BASIS_A_SHELLS, "B": BASIS_B_SHELLS}[name]
+    spec = {"A": BASIS_A_SHELLS, "B": BASIS_B_SHELLS, "C": BASIS_C_SHELLS}[name]
     rng = np.random.default_rng(BASIS_SEED[name])
     shells = {}
     for elem in ("O", "H"):
@@ -117,7 +126,7 @@ def make_basis(name: str) -> BasisTemplate:
             d = rng.uniform(0.2, 1.0, size=npr) if npr > 1 else np.ones(1)
             out.append((l, e, _contract_norm(e, d, l)))
         shells[elem] = out
-    return BasisTemplate(name=name, spherical=(name == "B"), shells=shells)
+    return BasisTemplate(name=name, spherical=(name != "A"), shells=shells)
 
 
 def _haar_rotation(rng: np.random.Generator) -> np.ndarray:
@@ -229,12 +238,14 @@ WORKLOADS = {
     "c0": dict(nwater=3, basis="A", geom_seed=200, dens_seed=300),
     "c1": dict(nwater=64, basis="A", geom_seed=201, dens_seed=301),
     "c2": dict(nwater=32, basis="B", geom_seed=202, dens_seed=302),
+    # g shells: 8 waters in the quadruple-zeta-shaped basis C (920 AOs)
+    "qz8": dict(nwater=8, basis="C", geom_seed=205, dens_seed=305),
 }
 
 
 def workload(name: str) -> Workload:
     """Single-molecule workloads c0 (3 waters, basis A), c1 (64 waters,
-    basis A) and c2 (32 waters, basis B)."""
+    basis A), c2 (32 waters, basis B) and qz8 (8 waters, basis C, up to g)."""
     spec = WORKLOADS[name]
     basis = make_basis(spec["basis"])
     elems, xyz = water_lattice(spec["nwater"], spec["geom_seed"])

@@ -231,12 +231,88 @@ def test_mixed_small(jkmod, torch_cuda, basis, nw):
     ej, ek = o.energies(wl.D, J, K)
     assert abs(ej[0] - ej0[0]) <= 1e-6 and abs(ek[0] - ek0[0]) <= 1e-6
     assert np.abs(J - J0).max() <= 1e-6 and np.abs(K - K0).max() <= 1e-6
-    # only the one-root classes are split, and some of their quartets are
-    # far enough for FP32
+    # every class is split by the per-quartet rule: the FP32 count is the
+    # oracle's count of quartets below the threshold (the two sides form
+    # Q independently, so a bound within rounding of the threshold may
+    # fall either way)
     st = plan.stats()
+    nsig, nlow = o.mixed_count(wl.mol, wl.D, wl.cutoff, 1e-4)
+    assert st.nquartets_evaluated == st.nquartets
+    assert abs(st.nquartets - nsig) <= 2 and abs(st.nquartets_fp32 - nlow) <= 2, (st.nquartets_fp32, nlow)
     assert 0 < st.nquartets_fp32 < st.nquartets
     _, J32, K32 = run_gpu(jkmod, torch_cuda, wl, precision="fp32", plan=plan)
     assert np.abs(J32 - J0).max() <= 1e-3
+    assert plan.stats().nquartets_fp32 == plan.stats().nquartets
+
+
+@pytest.mark.parametrize("basis,nw,thr", [("A", 5, 1e-3), ("B", 3, 1e-5), ("B", 4, 0.0), ("A", 3, 1e9)])
+def test_mixed_thresholds(jkmod, torch_cuda, basis, nw, thr):
+    """Threshold 0: nothing in FP32 (bit-identical to the FP64 build up to
+    atomic ordering); a huge threshold: everything in FP32; in between the
+    FP32 count follows the oracle's classification."""
+    wl = synth.small_workload(nw, basis, seed=150 + nw)
+    say("mixed threshold", basis, nw, thr)
+    plan, J64, K64 = run_gpu(jkmod, torch_cuda, wl)
+    _, J, K = run_gpu(jkmod, torch_cuda, wl, precision="mixed", plan=plan, mix_threshold=thr)
+    st = plan.stats()
+    nsig, nlow = o.mixed_count(wl.mol, wl.D, wl.cutoff, thr)
+    assert abs(st.nquartets_fp32 - nlow) <= 2
+    if thr == 0.0:
+        assert st.nquartets_fp32 == 0
+        assert np.abs(J - J64).max() <= 1e-13 and np.abs(K - K64).max() <= 1e-13
+    elif thr > 1e6:
+        assert st.nquartets_fp32 == st.nquartets
+    J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
+    ej0, ek0 = o.energies(wl.D, J0, K0)
+    ej, ek = o.energies(wl.D, J, K)
+    bound = 1e-6 if thr <= 1e-3 else 1e-3
+    assert np.abs(ej - ej0).max() <= bound and np.abs(ek - ek0).max() <= bound
+
+
+def test_jk_build_one_shot(jkmod, torch_cuda):
+    """jk_build (plan, execute, synchronise, destroy in one call) against
+    the oracle, FP64 and mixed."""
+    import torch
+    for basis, nw in (("A", 3), ("B", 2)):
+        wl = synth.small_workload(nw, basis, seed=230 + nw, nset=2)
+        say("jk_build", basis, nw)
+        J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
+        D = torch.from_numpy(wl.D).cuda()
+        J, K = jkmod.build(wl.mol, D, wl.cutoff, precision="fp64")
+        assert np.abs(J.cpu().numpy() - J0).max() <= TOL and np.abs(K.cpu().numpy() - K0).max() <= TOL
+        Jm, Km = jkmod.build(wl.mol, D, wl.cutoff, precision="mixed")
+        ej0, ek0 = o.energies(wl.D, J0, K0)
+        ej, ek = o.energies(wl.D, Jm.cpu().numpy(), Km.cpu().numpy())
+        assert np.abs(ej - ej0).max() <= 1e-6 and np.abs(ek - ek0).max() <= 1e-6
+    bad = synth.small_workload(1, "A", seed=1)
+    bad.mol.exps[0] = -1.0
+    with pytest.raises(jkmod.JKError) as e:
+        jkmod.build(bad.mol, torch.from_numpy(bad.D).cuda())
+    assert e.value.code == jkmod.JK_EINVAL
+
+
+def test_symmetry_check(jkmod, torch_cuda):
+    """JK_CHECK_SYMMETRY rejects a non-symmetric or non-finite D before the
+    build and accepts a symmetric one."""
+    import torch
+    wl = synth.small_workload(2, "B", seed=9)
+    plan = jkmod.Plan(wl.mol)
+    D = torch.from_numpy(wl.D).cuda()
+    flags = jkmod.JK_DO_J | jkmod.JK_DO_K | jkmod.JK_CHECK_SYMMETRY
+    J, K = plan.execute(D, flags=flags)
+    J0, K0 = plan.execute(D)
+    torch.cuda.synchronize()
+    assert torch.allclose(J, J0, atol=1e-13) and torch.allclose(K, K0, atol=1e-13)
+    Dn = D.clone()
+    Dn[0, 0, 1] += 1e-6
+    with pytest.raises(jkmod.JKError) as e:
+        plan.execute(Dn, flags=flags)
+    assert e.value.code == jkmod.JK_EINVAL and "symmetric" in str(e.value)
+    Dn = D.clone()
+    Dn[0, 2, 2] = float("nan")
+    with pytest.raises(jkmod.JKError) as e:
+        plan.execute(Dn, flags=flags)
+    assert e.value.code == jkmod.JK_EINVAL
 
 
 # ---------------------------------------------------------------------------
@@ -257,7 +333,9 @@ def test_full_size_sampled(jkmod, torch_cuda, name):
     wl = synth.workload(name)
     say("full", name, wl.mol.nshell, wl.mol.nao)
     plan, J, K = run_gpu(jkmod, torch_cuda, wl)
-    Q = plan.schwarz()
+    # the oracle's own Schwarz factors: the reference shares no screening
+    # decision with the GPU path
+    Q = o.schwarz(wl.mol)
     rng = np.random.default_rng(1)
     jp = _sample_pairs(wl.mol, rng, 4)
     kp = _sample_pairs(wl.mol, rng, 4)
@@ -280,9 +358,10 @@ def test_full_size_sampled(jkmod, torch_cuda, name):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("basis,nw", [("B", 6), ("A", 8)])
 def test_forced_families(jkmod, torch_cuda, basis, nw):
-    """Each class forced to family 1, then family 2 (where built), with row
-    mode allowed and then off, in FP64 and mixed precision, against the
-    oracle.  The tuner may pick any of these on another device."""
+    """Each class forced to family 1, 2, then 3 (where built), with row mode
+    for long bras, off, and for every bra, in FP64 and mixed precision,
+    against the oracle.  The tuner may pick any of these on another
+    device."""
     wl = synth.small_workload(nw, basis, seed=60 + nw)
     say("forced families", basis, nw)
     J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
@@ -290,11 +369,13 @@ def test_forced_families(jkmod, torch_cuda, basis, nw):
     Js0, Ks0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, omega=-0.4)
     Jd0, Kd0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1, dscreen=1e-7)
     try:
-        for fam in (1, 2):
+        for fam in (1, 2, 3):
             for row in (1, 2, 3):
+                if fam == 3 and row == 2:
+                    continue  # family 3 is row mode only: with row mode off it is the fallback's tiles
                 for c in jkmod.canonical_classes():
                     _, avail = jkmod.tune_get(*c, "fp64")
-                    jkmod.tune_set(*c, "fp64", fam if avail & fam else 0)
+                    jkmod.tune_set(*c, "fp64", fam if avail & (1 << (fam - 1)) else 0)
                     jkmod.tune_set_row(*c, "fp64", row)
                 _, Js, Ks = run_gpu(jkmod, torch_cuda, wl, omega=-0.4)
                 assert np.abs(Js - Js0).max() <= TOL and np.abs(Ks - Ks0).max() <= TOL, ("short range", fam, row)
@@ -306,7 +387,7 @@ def test_forced_families(jkmod, torch_cuda, basis, nw):
                     for c in jkmod.canonical_classes():
                         for p in ("fp64", "fp32"):
                             _, avail = jkmod.tune_get(*c, p)
-                            jkmod.tune_set(*c, p, fam if avail & fam else 0)
+                            jkmod.tune_set(*c, p, fam if avail & (1 << (fam - 1)) else 0)
                             jkmod.tune_set_row(*c, p, row)
                     _, J, K = run_gpu(jkmod, torch_cuda, wl, precision=prec)
                     if prec == "fp64":
