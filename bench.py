@@ -15,7 +15,9 @@ The same run measures every configuration of the workload set:
       on the c1 and c2 molecules: FP32 quartet fraction, speedup over FP64
       and the error against the oracle's stored values;
   c4  256 molecules of 1-8 waters with 4 densities each in one batched
-      build (recorded hipGraph), FP64 and mixed.
+      build (recorded hipGraph), FP64 and mixed;
+  qz8 8 waters in the quadruple-zeta-shaped basis up to g shells, FP64 and
+      mixed.
 Per build: builds/s and quartets/s from a plain timed loop (no per-kernel
 events), then a separate profiled pass (HIP events around every class
 kernel) for the per-kernel breakdown and the dominant kernel's roofline.
@@ -27,6 +29,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import functools
 import json
 import os
 import re
@@ -44,6 +47,7 @@ WORKLOAD_TEXT = {
     "c0": "3 waters, basis A (6-31G*-shaped, Cartesian), 57 AOs, 1 density, cutoff 1e-13",
     "c1": "64 waters 4x4x4 lattice, basis A (6-31G*-shaped, Cartesian), 1216 AOs, 1 density, cutoff 1e-13",
     "c2": "32 waters, basis B (TZ2P-shaped, spherical, up to f), 1376 AOs, 1 density, cutoff 1e-13",
+    "qz8": "8 waters, basis C (QZ-shaped, spherical, up to g), 920 AOs, 1 density, cutoff 1e-13",
 }
 BATCH_TEXT = ("256 molecules of 1-8 waters, half basis A (Cartesian), half basis B (spherical), "
               "4 densities each, cutoff 1e-13")
@@ -98,21 +102,41 @@ def hbm_traffic(workload: str, kernel: str):
 
 
 def golden(name):
-    with open(os.path.join(GOLDEN, f"{name}_jk.json")) as f:
+    path = os.path.join(GOLDEN, f"{name}_jk.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
         return json.load(f)
+
+
+STEP_MS = {}  # per-step device times (ms) of the last timed_loop, by id(run)
 
 
 def timed_loop(run, steps, warmup, torch):
     """Mean seconds per call of run() over `steps` calls after `warmup`,
-    bracketed by device synchronisations; nothing else in the loop."""
+    bracketed by device synchronisations; nothing else in the loop but an
+    event on the stream between calls (for the median and minimum)."""
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record()
+    for k in range(steps):
         run()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    dt = (time.perf_counter() - t0) / steps
+    STEP_MS[id(run)] = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+    return dt
+
+
+def step_stats(run):
+    """Median and minimum device ms per call of the last timed_loop(run)."""
+    v = STEP_MS.get(id(run), [])
+    if not v:
+        return {}
+    return {"ms_median": v[len(v) // 2], "ms_min": v[0]}
 
 
 def profiled(plan, run, steps, torch):
@@ -164,6 +188,8 @@ def errors_vs_golden(g, D, J, K):
     """max |dJ|, |dK| over the stored elements and dE_J, dE_K (closed-shell
     reading E_J = 2 Tr(DJ), E_K = Tr(DK)) against the oracle's values."""
     import numpy as np
+    if g is None:
+        return None
     Jh, Kh, Dh = J[0].cpu().numpy(), K[0].cpu().numpy(), D[0]
     ej, ek = 2.0 * float(np.sum(Dh * Jh)), float(np.sum(Dh * Kh))
     return {"max_dJ": float(np.abs(Jh.ravel()[::g["stride"]] - np.asarray(g["J"])).max()),
@@ -188,7 +214,7 @@ def bench_molecule(name, args, torch, jk, synth, steps, warmup):
     res = {"workload": f"{name}: {WORKLOAD_TEXT[name]}", "nquartets": st.nquartets,
            "nprim_quartets": st.nprim_quartets, "plan_seconds": time.perf_counter() - t0,
            "model_flops_per_build": st.model_flops, "steps": steps, "warmup": warmup}
-    for prec in ("fp64", "mixed"):
+    for prec in args.precisions.split(","):
         def run():
             plan.execute(D, J, K, precision=prec, mix_threshold=args.mix_threshold)
         dt = timed_loop(run, steps, warmup, torch)
@@ -201,7 +227,7 @@ def bench_molecule(name, args, torch, jk, synth, steps, warmup):
         ms64 = sum(k["ms"] for k in kern.values() if k["precision"] == "fp64") / psteps
         ms32 = sum(k["ms"] for k in kern.values() if k["precision"] == "fp32") / psteps
         t_bound = f64 / (PEAK_FP64_VECTOR * 1e12) + f32 / (PEAK_FP32_VECTOR * 1e12)
-        r = {"ms_per_step": dt * 1e3, "builds_per_s": 1.0 / dt, "quartets_per_s": st.nquartets / dt,
+        r = {"ms_per_step": dt * 1e3, **step_stats(run), "builds_per_s": 1.0 / dt, "quartets_per_s": st.nquartets / dt,
              "prim_quartets_per_s": st.nprim_quartets / dt, "model_tflops": st.model_flops / dt / 1e12,
              "frac_of_vector_roofline": t_bound / dt, "fp32_quartets": stp.nquartets_fp32,
              "fp32_fraction": stp.nquartets_fp32 / st.nquartets, "kernel_ms_fp64": ms64, "kernel_ms_fp32": ms32,
@@ -210,14 +236,16 @@ def bench_molecule(name, args, torch, jk, synth, steps, warmup):
         r["top_kernels"] = [{"kernel": n, "ms_per_build": k["ms"] / psteps,
                              "tflops": k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0}
                             for n, k in top]
+        ev = (f"vs oracle max|dJ| {err['max_dJ']:.1e} max|dK| {err['max_dK']:.1e} dE_J {err['dE_J']:.1e} "
+              f"dE_K {err['dE_K']:.1e}") if err else "no stored oracle values"
         log(f"{name} {prec}: {dt * 1e3:.2f} ms/build, {st.nquartets / dt:.3e} quartets/s, fp32 fraction "
-            f"{r['fp32_fraction']:.3f}; kernels fp64 {ms64:.1f} ms fp32 {ms32:.1f} ms; vs oracle max|dJ| "
-            f"{err['max_dJ']:.1e} max|dK| {err['max_dK']:.1e} dE_J {err['dE_J']:.1e} dE_K {err['dE_K']:.1e}")
+            f"{r['fp32_fraction']:.3f}; kernels fp64 {ms64:.1f} ms fp32 {ms32:.1f} ms; {ev}")
         for n, k in top:
             log(f"  {n:46s} {k['ms'] / psteps:8.3f} ms/build  {k['launches'] / psteps:4.0f} launches  "
                 f"{k['flops'] / (k['ms'] * 1e-3) / 1e12 if k['ms'] > 0 else 0:6.2f} TF/s")
         res[prec] = r
-    res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    if "fp64" in res and "mixed" in res:
+        res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
     if name == "c1" and not args.no_dscreen:
         res["density_screening"] = bench_dscreen(args, torch, plan, wl, res["fp64"]["ms_per_step"] * 1e-3, steps,
                                                  warmup)
@@ -255,12 +283,14 @@ def bench_batch(args, torch, jk, synth, steps, warmup):
             de = max(de, float(np.abs(ej - np.asarray(gm["E_J"])).max()), float(np.abs(ek - np.asarray(gm["E_K"])).max()))
         return {"max_dJ": dj, "max_dK": dk, "max_dE": de}
 
-    for precision in ("fp64", "mixed"):
+    for precision in args.precisions.split(","):
         b = jk.Batch(plans, nset=nset, precision=precision, mix_threshold=args.mix_threshold)
-        dt = timed_loop(lambda: b.execute(Ds, Js, Ks), steps, warmup, torch)
+        def run():
+            b.execute(Ds, Js, Ks)
+        dt = timed_loop(run, steps, warmup, torch)
         nev, n32 = b.stats()
         err = errors()
-        res[precision] = {"ms_per_step": dt * 1e3, "molecule_builds_per_s": len(wls) / dt,
+        res[precision] = {"ms_per_step": dt * 1e3, **step_stats(run), "molecule_builds_per_s": len(wls) / dt,
                           "density_builds_per_s": len(wls) * nset / dt, "quartets_per_s": nq / dt,
                           "fp32_quartets": n32, "fp32_fraction": n32 / max(nev, 1), "vs_oracle": err}
         log(f"c4 {precision}: {dt * 1e3:.1f} ms per batch ({len(wls) / dt:.0f} molecule builds/s), fp32 fraction "
@@ -275,7 +305,8 @@ def bench_batch(args, torch, jk, synth, steps, warmup):
         res[precision]["one_by_one_ms"] = dts * 1e3
         res[precision]["speedup_vs_one_by_one"] = dts / dt
         log(f"c4 {precision}: one by one {dts * 1e3:.1f} ms")
-    res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    if "fp64" in res and "mixed" in res:
+        res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
     for p in plans:
         p.close()
     return res
@@ -405,9 +436,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed steps of the headline (c1) builds")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--configs", default="c1,c2,c4", help="comma list of c1, c2, c4 (c1 is always run)")
+    ap.add_argument("--configs", default="c1,c2,c4,qz8", help="comma list of c1, c2, c4, qz8 (c1 is always run)")
     ap.add_argument("--steps-other", type=int, default=5, help="most timed steps of c2 and c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=sorted(WORKLOAD_TEXT) + ["c4"], default=None,
+                    help="time one molecule alone and print its result (for profiler runs)")
+    ap.add_argument("--precisions", default="fp64,mixed",
+                    help="builds timed per molecule (fp64 is needed for the headline value)")
     ap.add_argument("--no-dscreen", action="store_true", help="skip the incremental (density-screened) build")
     ap.add_argument("--micro", action="store_true", help="only the appendix-B style micro-benchmarks")
     ap.add_argument("--dscreen", type=float, default=1e-10, help="density screening threshold")
@@ -443,6 +478,11 @@ def main():
     which = [c.strip() for c in args.configs.split(",") if c.strip()]
     so, wo = max(1, min(args.steps, args.steps_other)), max(1, min(args.warmup, 2))
 
+    if args.only:
+        # one molecule alone (the profiler runs): its result, not the headline line
+        f = bench_batch if args.only == "c4" else functools.partial(bench_molecule, args.only)
+        print(json.dumps({args.only: f(args, torch, jk, synth, args.steps, args.warmup)}), flush=True)
+        return
     c1 = bench_molecule("c1", args, torch, jk, synth, args.steps, args.warmup)
     r64 = c1["fp64"]
     out = {"metric": METRIC, "value": r64["builds_per_s"], "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
@@ -458,17 +498,18 @@ def main():
     # config 3: the mixed split on the c1 and c2 molecules
     c3 = {}
     for n in ("c1", "c2"):
-        if n in out["configs"]:
+        if n in out["configs"] and "mixed" in out["configs"][n]:
             m = out["configs"][n]["mixed"]
             c3[n] = {"fp32_fraction": m["fp32_fraction"], "speedup_vs_fp64": m["speedup_vs_fp64"],
                      "builds_per_s": m["builds_per_s"], "quartets_per_s": m["quartets_per_s"],
                      "frac_of_vector_roofline": m["frac_of_vector_roofline"],
-                     "max_dJ": m["vs_oracle"]["max_dJ"], "max_dK": m["vs_oracle"]["max_dK"],
-                     "dE_J": m["vs_oracle"]["dE_J"], "dE_K": m["vs_oracle"]["dE_K"],
+                     "vs_oracle": m["vs_oracle"],
                      "threshold": args.mix_threshold}
     out["configs"]["c3"] = c3
     if "c4" in which:
         out["configs"]["c4"] = bench_batch(args, torch, jk, synth, so, wo)
+    if "qz8" in which:
+        out["configs"]["qz8"] = bench_molecule("qz8", args, torch, jk, synth, so, wo)
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(synth.workload("c1"), args.cpu_seconds)

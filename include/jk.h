@@ -68,7 +68,7 @@ enum {
 };
 
 #define JK_LMAX 4       /* highest angular momentum the basis format admits (g) */
-#define JK_LMAX_BUILT 3 /* highest one with built kernels (f); l = 4 -> JK_EUNSUPPORTED */
+#define JK_LMAX_BUILT 4 /* highest one with built kernels (g) */
 #define JK_MAXPRIM 16   /* most primitives per shell */
 
 /* Basis description, host memory, owned by the caller, read only during the
@@ -77,8 +77,7 @@ typedef struct {
     int32_t nshell;
     int32_t natom;
     int32_t spherical;      /* 0 Cartesian, 1 real solid harmonics */
-    const int32_t *l;       /* [nshell] 0..JK_LMAX (l > JK_LMAX: JK_EINVAL;
-                               JK_LMAX_BUILT < l <= JK_LMAX: JK_EUNSUPPORTED) */
+    const int32_t *l;       /* [nshell] 0..JK_LMAX (l > JK_LMAX: JK_EINVAL) */
     const int32_t *nprim;   /* [nshell] 1..JK_MAXPRIM */
     const int32_t *atom;    /* [nshell] 0..natom-1 */
     const double *exps;     /* [sum nprim] > 0, grouped by shell in shell order */
@@ -140,7 +139,6 @@ int jk_plan_schwarz(const jk_plan *plan, double *Q_host);
  */
 int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int32_t precision,
                double mix_threshold, double omega, double *J, double *K, void *stream);
-
 
 /*
  * Density screening for direct SCF (Section 2: the screening of the J and K

@@ -991,9 +991,15 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
             const int ft = f == 3 ? tile_fallback(c.li, c.lj, c.lk, c.ll) : f;
             const int slot = (int)(2 * ci + pr) * 4;  // + kind
             const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);
-            const bool longrows = c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
+            // the double-precision pass of the mixed split runs as tiles: its
+            // quartets are the first few kets of each bra (largest Schwarz
+            // factors), a fraction of one row-mode pass per bra, and tiles
+            // past them end at their first ket
+            const bool tiles_only = a.sel == SEL_HI;
+            const bool longrows = !tiles_only && c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
                                   row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
-            const bool shortrows = c.row_short[pr] && c.nsrow > 0 && e.srow[f - 1][pr] && (longrows || c.nrow == 0) &&
+            const bool shortrows = !tiles_only && c.row_short[pr] && c.nsrow > 0 && e.srow[f - 1][pr] &&
+                                   (longrows || c.nrow == 0) &&
                                    row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 1, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
             if (longrows || shortrows) {
                 a.bra_list = c.d_bra;

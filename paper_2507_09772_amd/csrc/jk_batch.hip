@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -88,6 +89,10 @@ __global__ void kb_finalize(const MolDesc *mols, int nset) {
     }
 }
 
+__global__ void kb_zero_i32(int *p, int n) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0;
+}
+
 __global__ void kb_zero_u64(unsigned long long *p, int n) {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) p[t] = 0ull;
 }
@@ -116,7 +121,17 @@ struct jk_batch {
     BatchDesc *d_desc = nullptr;
     std::vector<Group> groups;
     unsigned long long *d_ctr = nullptr;  // evaluated quartets per descriptor (NSEL_SLOTS counters each)
+    // persistent form: per precision, the (descriptor, task) queue of the
+    // one- and two-root family-1 row tasks, its length, LDS and grid
+    struct Persist {
+        int32_t *items = nullptr;
+        int nitems = 0;
+        size_t lds = 0;
+        int grid = 0;
+    } persist[2];
+    int *d_pctr = nullptr;  // queue heads, one per precision
     std::vector<int64_t> fixed;           // per descriptor: its quartet count when not counted on the device
+    std::vector<int> dprec;               // per descriptor: kernel precision (0 FP64, 1 FP32)
     int32_t *d_tasks = nullptr;  // row tasks of the row-kind descriptors
     int nctr = 0;
     int64_t max_elems = 0;      // largest nset * naoc^2 over the molecules
@@ -126,6 +141,12 @@ struct jk_batch {
     MolDesc *h_stage = nullptr;  // pinned staging for pointer updates
     hipEvent_t stage_ev = nullptr;
     hipStream_t cap = nullptr;
+    // class launches are independent (they only add into J', K' and the
+    // pair-ordered J'): the graph holds them as nbranch parallel branches
+    static constexpr int MAXBRANCH = 8;
+    int nbranch = 1;
+    hipStream_t branch[MAXBRANCH] = {};
+    hipEvent_t fork = nullptr, join[MAXBRANCH] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
@@ -143,6 +164,11 @@ struct jk_batch {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
+        for (int k = 1; k < MAXBRANCH; ++k) {  // branch[0] is cap
+            if (branch[k]) (void)hipStreamDestroy(branch[k]);
+            if (join[k]) (void)hipEventDestroy(join[k]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
         if (stage_ev) (void)hipEventDestroy(stage_ev);
         if (h_stage) (void)hipHostFree(h_stage);
         for (void *p : allocs) (void)hipFree(p);
@@ -164,11 +190,31 @@ static int record(jk_batch *b) {
         hipLaunchKernelGGL(kb_dmax_all, dim3(nm), dim3(256), 0, s, b->d_mol);
         HIPCHK(hipGetLastError());
     }
+    // fork: the class launches go round-robin (heaviest first) onto the
+    // branch streams, which join before the scatter and finalisation
+    HIPCHK(hipEventRecord(b->fork, s));
+    for (int k = 1; k < b->nbranch; ++k) HIPCHK(hipStreamWaitEvent(b->branch[k], b->fork, 0));
+    if (b->d_pctr) {
+        hipLaunchKernelGGL(kb_zero_i32, dim3(1), dim3(64), 0, s, b->d_pctr, 2);
+        HIPCHK(hipGetLastError());
+    }
+    int br = 0;
+    for (int pr = 0; pr < 2; ++pr) {
+        const jk_batch::Persist &q = b->persist[pr];
+        if (q.nitems > 0)
+            HIPCHK(launch_k1_persist(pr, b->d_desc, q.items, q.nitems, b->d_pctr + pr, q.lds, q.grid,
+                                     b->branch[br++ % b->nbranch]));
+    }
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         const Group &g = b->groups[gi];
         const ClassEntry &e = g_classes[g.cid];
-        if (g.kind == 1) HIPCHK(e.batch_row[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, g.lds, s));
-        else HIPCHK(e.batch[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, s));
+        hipStream_t bs = b->branch[(br + gi) % b->nbranch];
+        if (g.kind == 1) HIPCHK(e.batch_row[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, g.lds, bs));
+        else HIPCHK(e.batch[g.fam - 1][g.pr](b->d_desc + g.first, g.count, g.total_tiles, bs));
+    }
+    for (int k = 1; k < b->nbranch; ++k) {
+        HIPCHK(hipEventRecord(b->join[k], b->branch[k]));
+        HIPCHK(hipStreamWaitEvent(s, b->join[k], 0));
     }
     hipLaunchKernelGGL(kb_jp_scatter, dim3(grid_rows(b->max_jpt), nm), dim3(256), 0, s, b->d_mol, b->nset);
     HIPCHK(hipGetLastError());
@@ -322,6 +368,9 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             }
         }
     }
+    std::vector<int32_t> hdesc_tasks;  // work units per descriptor
+    std::vector<double> dwork;         // model FLOPs per descriptor
+    std::vector<int32_t> dclass;       // class id per descriptor
     for (auto &kv : byg) {
         auto &v = kv.second;
         std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
@@ -339,6 +388,10 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             x.second.tile_base = (int32_t)tiles;
             tiles += x.second.pad[1];
             g.work += x.first;
+            hdesc_tasks.push_back(x.second.pad[1]);
+            dwork.push_back(x.first);
+            dclass.push_back(g.cid);
+            b->dprec.push_back(g.pr);
             b->hdesc.push_back(x.second);
         }
         if (tiles > INT32_MAX) return fail(JK_EINVAL, "too many tiles in one class group");
@@ -346,12 +399,7 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         b->groups.push_back(g);
     }
     std::stable_sort(b->groups.begin(), b->groups.end(), [](const Group &x, const Group &y) { return x.work > y.work; });
-    // evaluated-quartet counters per descriptor (mixed precision only: with
-    // every quartet selected the count is the descriptor's); row tasks to
-    // the device
-    const size_t per = (size_t)NSEL_SLOTS * NSEL_STRIDE;
-    b->nctr = (int)(std::max<size_t>(b->hdesc.size(), 1) * per);
-    if ((rc = b->alloc(&b->d_ctr, b->nctr))) return rc;
+    // row tasks to the device
     if ((rc = b->alloc(&b->d_tasks, alltasks.size()))) return rc;
     if (!alltasks.empty())
         HIPCHK(hipMemcpy(b->d_tasks, alltasks.data(), sizeof(int32_t) * alltasks.size(), hipMemcpyHostToDevice));
@@ -362,6 +410,35 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             if (g.kind == 1) d.a.row_pos = b->d_tasks + d.pad[2];
         }
     }
+    // persistent form (JK_BATCH_PERSIST, default on): the family-1 row tasks of
+    // the one- and two-root classes leave their per-class launches for one
+    // queue per precision, ordered by work per task (heaviest first)
+    std::vector<std::vector<std::pair<double, std::pair<int32_t, int32_t>>>> pitems(2);
+    {
+        const char *pe = getenv("JK_BATCH_PERSIST");
+        const bool on = !(pe && pe[0] == '0');
+        std::vector<Group> keep;
+        for (const Group &g : b->groups) {
+            const int li = g.cid / 125, lj = (g.cid / 25) % 5, lk = (g.cid / 5) % 5, ll = g.cid % 5;
+            if (!(on && g.kind == 1 && g.fam == 1 && persist_class(li, lj, lk, ll))) {
+                keep.push_back(g);
+                continue;
+            }
+            for (int k = 0; k < g.count; ++k) {
+                const int di = g.first + k;
+                const int ntask = hdesc_tasks[di];
+                const double w = dwork[di] / std::max(ntask, 1);
+                for (int t = 0; t < ntask; ++t) pitems[g.pr].push_back({w, {di, t}});
+            }
+            b->persist[g.pr].lds = std::max(b->persist[g.pr].lds, g.lds);
+        }
+        b->groups = keep;
+    }
+    // evaluated-quartet counters per descriptor (mixed precision only: with
+    // every quartet selected the count is the descriptor's)
+    const size_t per = (size_t)NSEL_SLOTS * NSEL_STRIDE;
+    b->nctr = (int)(std::max<size_t>(b->hdesc.size(), 1) * per);
+    if ((rc = b->alloc(&b->d_ctr, b->nctr))) return rc;
     b->fixed.assign(b->hdesc.size(), -1);
     for (size_t k = 0; k < b->hdesc.size(); ++k) {
         BatchDesc &d = b->hdesc[k];
@@ -371,14 +448,49 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             d.a.nsel = nullptr;
             b->fixed[k] = d.a.nq;
         }
-        d.pad[0] = d.pad[1] = d.pad[2] = 0;
+        d.pad[0] = dclass[k];  // the class (the persistent kernel's switch)
+        d.pad[1] = d.pad[2] = 0;
     }
     if ((rc = b->alloc(&b->d_desc, b->hdesc.size())) || (rc = b->alloc(&b->d_mol, nmol))) return rc;
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int pr = 0; pr < 2; ++pr) {
+        auto &v = pitems[pr];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+        std::vector<int32_t> flat;
+        flat.reserve(2 * v.size());
+        for (const auto &it : v) {
+            flat.push_back(it.second.first);
+            flat.push_back(it.second.second);
+        }
+        if (v.size() > (size_t)INT32_MAX / 2) return fail(JK_EINVAL, "too many persistent work items");
+        jk_batch::Persist &q = b->persist[pr];
+        if ((rc = b->alloc(&q.items, flat.size()))) return rc;
+        HIPCHK(hipMemcpy(q.items, flat.data(), sizeof(int32_t) * flat.size(), hipMemcpyHostToDevice));
+        q.nitems = (int)v.size();
+        // workgroups: enough 64-lane waves to fill every CU several times
+        q.grid = (int)std::min<int64_t>(q.nitems, (int64_t)std::max(ncu, 1) * 16);
+    }
+    if ((rc = b->alloc(&b->d_pctr, 2))) return rc;
     if (!b->hdesc.empty())
         HIPCHK(hipMemcpy(b->d_desc, b->hdesc.data(), sizeof(BatchDesc) * b->hdesc.size(), hipMemcpyHostToDevice));
     HIPCHK(hipHostMalloc((void **)&b->h_stage, sizeof(MolDesc) * nmol, hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&b->stage_ev, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    // parallel branches of the graph (JK_BATCH_BRANCHES, default 4; all
+    // streams at the default priority)
+    {
+        const char *nb = getenv("JK_BATCH_BRANCHES");
+        const int v = nb && *nb ? atoi(nb) : 4;
+        b->nbranch = std::max(1, std::min(v, (int)jk_batch::MAXBRANCH));
+    }
+    b->branch[0] = b->cap;
+    for (int k = 1; k < b->nbranch; ++k) {
+        HIPCHK(hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+    }
+    HIPCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
     *out = b.release();
     return JK_OK;
 }
@@ -435,17 +547,15 @@ extern "C" int jk_batch_stats(const jk_batch *b, int64_t *nquartets, int64_t *nq
     if (!raw.empty())
         HIPCHK(hipMemcpy(raw.data(), b->d_ctr, sizeof(unsigned long long) * raw.size(), hipMemcpyDeviceToHost));
     int64_t n = 0, n32 = 0;
-    for (const Group &g : b->groups)
-        for (int k = 0; k < g.count; ++k) {
-            const size_t d = (size_t)(g.first + k);
-            int64_t c = b->fixed[d];
-            if (c < 0) {
-                c = 0;
-                for (int j = 0; j < NSEL_SLOTS; ++j) c += (int64_t)raw[d * per + (size_t)j * NSEL_STRIDE];
-            }
-            n += c;
-            if (g.pr == 1) n32 += c;
+    for (size_t d = 0; d < b->hdesc.size(); ++d) {
+        int64_t c = b->fixed[d];
+        if (c < 0) {
+            c = 0;
+            for (int j = 0; j < NSEL_SLOTS; ++j) c += (int64_t)raw[d * per + (size_t)j * NSEL_STRIDE];
         }
+        n += c;
+        if (b->dprec[d] == 1) n32 += c;
+    }
     if (nquartets) *nquartets = n;
     if (nquartets_fp32) *nquartets_fp32 = n32;
     return JK_OK;

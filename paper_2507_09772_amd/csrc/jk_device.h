@@ -108,8 +108,9 @@ __device__ __forceinline__ void rys1(double T, const R *__restrict__ boys, R &u,
 
 // The same rule in two stages, so that the grid row of the next primitive
 // quartet can be in flight while the current one is evaluated: rys1_fetch
-// loads the row (lanes beyond the table end load nothing) and rys1_eval
-// gives exactly the values of rys1.
+// loads the row (lanes beyond the table end load nothing and leave the row
+// as it was: rys1_eval does not read it for them) and rys1_eval gives
+// exactly the values of rys1.
 template <typename R>
 struct Rys1Row {
     static constexpr int NT = sizeof(R) == 8 ? 7 : 4;  // Taylor terms
@@ -124,10 +125,6 @@ __device__ __forceinline__ void rys1_fetch(double T, const R *__restrict__ boys,
         const R *src = boys + j * (JKT_BOYS_MMAX + 1);
 #pragma unroll
         for (int k = 0; k <= Rys1Row<R>::NT; ++k) row.f[k] = src[k];
-    } else {
-        row.d = (R)0;
-#pragma unroll
-        for (int k = 0; k <= Rys1Row<R>::NT; ++k) row.f[k] = (R)0;
     }
 }
 template <typename R>
@@ -178,11 +175,8 @@ __device__ __forceinline__ void rys2_fetch(double T, const double *__restrict__ 
         const double *src = mom + j * JKT_MOM_COLS;
 #pragma unroll
         for (int k = 0; k < JKT_MOM_COLS; ++k) row.f[k] = src[k];
-    } else {
-        row.d = 0.0;
-#pragma unroll
-        for (int k = 0; k < JKT_MOM_COLS; ++k) row.f[k] = 0.0;
     }
+    // (beyond the grid the row keeps its contents: rys2_eval does not read it)
 }
 
 __device__ __forceinline__ void rys2_eval(double T, const Rys2Row &row, double (&u)[2], double (&w)[2]) {

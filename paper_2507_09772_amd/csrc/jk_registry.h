@@ -6,7 +6,7 @@
 
 namespace jk {
 
-constexpr int LMAX_BUILT = 3;  // classes instantiated up to (ff|ff)
+constexpr int LMAX_BUILT = 4;  // classes instantiated up to (gg|gg)
 
 using Launcher = hipError_t (*)(const JkArgs &, hipStream_t);
 // Batched builds: the tiles of many descriptors (molecules) in one launch.
@@ -35,6 +35,13 @@ inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj
 // LDS budget of one row-mode workgroup (dynamic shared memory; gfx950 has
 // 160 KB per CU, kernels above 64 KB opt in through a function attribute).
 constexpr int ROW_LDS_MAX = 128 * 1024;
+
+// Persistent form of the batched builds (kern_persist.hip): the family-1
+// 64-lane row tasks of the one- and two-root classes of every molecule in
+// one launch over a queue of (descriptor, task) items.
+bool persist_class(int li, int lj, int lk, int ll);
+hipError_t launch_k1_persist(int pr, const BatchDesc *descs, const int32_t *items, int nitems, int *counter, size_t lds,
+                             int grid, hipStream_t s);
 
 // Indexed by class_id(li, lj, lk, ll); zero-initialised, filled by the
 // static initialisers of the kernel units when the library loads.

@@ -138,9 +138,14 @@ static hipError_t launch_k2_batch(const BatchDesc *d, int ndesc, int total, hipS
     return hipGetLastError();
 }
 
+// Classes with a g shell (l = 4) get the single-molecule kernels only (no
+// 64-lane short-bra row kernels and no batched kernels), which keeps their
+// compile time in bounds: short bras run as tiles, and batched builds of
+// such molecules report JK_EUNSUPPORTED.
 template <int LK, int LL>
 static void reg_one() {
     constexpr int LI = JK_LI, LJ = JK_LJ;
+    constexpr bool FULL = LI < 4;
     if constexpr (LK >= LL && (LK < LI || (LK == LI && LL <= LJ))) {
         ClassEntry &e = g_classes[class_id(LI, LJ, LK, LL)];
         if constexpr (has_family1(LI, LJ, LK, LL)) {
@@ -148,34 +153,42 @@ static void reg_one() {
             e.tiles[0][1] = &launch_k1<LI, LJ, LK, LL, float, MODE_JK>;
             e.row[0][0] = &launch_row<LI, LJ, LK, LL, double, 256>;
             e.row[0][1] = &launch_row<LI, LJ, LK, LL, float, 256>;
-            e.srow[0][0] = &launch_row<LI, LJ, LK, LL, double, 64>;
-            e.srow[0][1] = &launch_row<LI, LJ, LK, LL, float, 64>;
-            e.batch_row[0][0] = &launch_row_batch<LI, LJ, LK, LL, double>;
-            e.batch_row[0][1] = &launch_row_batch<LI, LJ, LK, LL, float>;
-            e.batch[0][0] = &launch_k1_batch<LI, LJ, LK, LL, double>;
-            e.batch[0][1] = &launch_k1_batch<LI, LJ, LK, LL, float>;
+            if constexpr (FULL) {
+                e.srow[0][0] = &launch_row<LI, LJ, LK, LL, double, 64>;
+                e.srow[0][1] = &launch_row<LI, LJ, LK, LL, float, 64>;
+                e.batch_row[0][0] = &launch_row_batch<LI, LJ, LK, LL, double>;
+                e.batch_row[0][1] = &launch_row_batch<LI, LJ, LK, LL, float>;
+                e.batch[0][0] = &launch_k1_batch<LI, LJ, LK, LL, double>;
+                e.batch[0][1] = &launch_k1_batch<LI, LJ, LK, LL, float>;
+            }
         }
         if constexpr (has_family2(LI, LJ, LK, LL)) {
             e.tiles[1][0] = &launch_k2<LI, LJ, LK, LL, double, MODE_JK>;
             e.tiles[1][1] = &launch_k2<LI, LJ, LK, LL, float, MODE_JK>;
             e.row[1][0] = &launch_row2<LI, LJ, LK, LL, double, 256>;
             e.row[1][1] = &launch_row2<LI, LJ, LK, LL, float, 256>;
-            e.srow[1][0] = &launch_row2<LI, LJ, LK, LL, double, 64>;
-            e.srow[1][1] = &launch_row2<LI, LJ, LK, LL, float, 64>;
-            e.batch_row[1][0] = &launch_row2_batch<LI, LJ, LK, LL, double>;
-            e.batch_row[1][1] = &launch_row2_batch<LI, LJ, LK, LL, float>;
+            if constexpr (FULL) {
+                e.srow[1][0] = &launch_row2<LI, LJ, LK, LL, double, 64>;
+                e.srow[1][1] = &launch_row2<LI, LJ, LK, LL, float, 64>;
+                e.batch_row[1][0] = &launch_row2_batch<LI, LJ, LK, LL, double>;
+                e.batch_row[1][1] = &launch_row2_batch<LI, LJ, LK, LL, float>;
+            }
             e.row_fixed[1][0] = K2RowLds<LI, LJ, LK, LL>::template fixed<double>();
             e.row_fixed[1][1] = K2RowLds<LI, LJ, LK, LL>::template fixed<float>();
-            e.batch[1][0] = &launch_k2_batch<LI, LJ, LK, LL, double>;
-            e.batch[1][1] = &launch_k2_batch<LI, LJ, LK, LL, float>;
+            if constexpr (FULL) {
+                e.batch[1][0] = &launch_k2_batch<LI, LJ, LK, LL, double>;
+                e.batch[1][1] = &launch_k2_batch<LI, LJ, LK, LL, float>;
+            }
         }
         if constexpr (has_family3(LI, LJ, LK, LL)) {
             e.row[2][0] = &launch_row3<LI, LJ, LK, LL, double, 256>;
             e.row[2][1] = &launch_row3<LI, LJ, LK, LL, float, 256>;
-            e.srow[2][0] = &launch_row3<LI, LJ, LK, LL, double, 64>;
-            e.srow[2][1] = &launch_row3<LI, LJ, LK, LL, float, 64>;
-            e.batch_row[2][0] = &launch_row3_batch<LI, LJ, LK, LL, double>;
-            e.batch_row[2][1] = &launch_row3_batch<LI, LJ, LK, LL, float>;
+            if constexpr (FULL) {
+                e.srow[2][0] = &launch_row3<LI, LJ, LK, LL, double, 64>;
+                e.srow[2][1] = &launch_row3<LI, LJ, LK, LL, float, 64>;
+                e.batch_row[2][0] = &launch_row3_batch<LI, LJ, LK, LL, double>;
+                e.batch_row[2][1] = &launch_row3_batch<LI, LJ, LK, LL, float>;
+            }
             e.row_fixed[2][0] = K3Cfg<LI, LJ, LK, LL>::template wave_bytes<double>();
             e.row_fixed[2][1] = K3Cfg<LI, LJ, LK, LL>::template wave_bytes<float>();
         }

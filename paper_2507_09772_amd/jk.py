@@ -287,7 +287,7 @@ def tune_load(path):
     _check(lib().jk_tune_load(os.fsencode(path)))
 
 
-def canonical_classes(lmax=3):
+def canonical_classes(lmax=4):
     return [(i, j, k, l) for i in range(lmax + 1) for j in range(i + 1) for k in range(i + 1)
             for l in range(k + 1) if k < i or (k == i and l <= j)]
 

@@ -54,7 +54,7 @@ def _set(arr, i, v):
 
 @pytest.mark.parametrize("mol,code", [
     (lambda: _bad(l=lambda a: _set(a, 2, 9)), -1),
-    (lambda: _bad(l=lambda a: _set(a, 2, 4)), -2),
+    (lambda: _bad(l=lambda a: _set(a, 2, 5)), -1),
     (lambda: _bad(nprim=lambda a: _set(a, 0, 0)), -1),
     (lambda: _bad(atom=lambda a: _set(a, 1, 99)), -1),
     (lambda: _bad(exps=lambda a: _set(a, 3, -1.0)), -1),
@@ -91,12 +91,18 @@ def test_shipped_tuning_table_is_applied(jkmod):
     """Every entry of the shipped per-device table reaches the library (the
     table is read after the kernel classes have registered)."""
     path = os.path.join(ROOT, "paper_2507_09772_amd", "tune_gfx950.txt")
-    rows = [list(map(int, l.split())) for l in open(path) if l.strip() and not l.startswith("#")]
+    rows = [list(map(int, l.split())) for l in open(path)
+            if l.strip() and not l.startswith("#") and not l.startswith("shape")]
     assert rows
     for r in rows:
         li, lj, lk, ll, pr, fam = r[:6]
         got, avail = jkmod.tune_get(li, lj, lk, ll, "fp32" if pr == 2 else "fp64")
-        assert got == fam and avail & fam, r
+        assert got == fam and avail & (1 << (fam - 1)), r
+    # the task-shape lines parse and name canonical classes
+    shapes = [l.split()[1:] for l in open(path) if l.startswith("shape")]
+    for sh in shapes:
+        assert len(sh) == 6
+        jkmod.tune_set_shape(*map(int, sh))
 
 
 def test_tuning_validation(jkmod):

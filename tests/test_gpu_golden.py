@@ -33,7 +33,7 @@ def torch_jk():
     return torch, jk
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
+@pytest.mark.parametrize("name", ["c1", "c2", "qz8"])
 def test_full_size_against_golden(torch_jk, name):
     torch, jk = torch_jk
     g = golden(name)

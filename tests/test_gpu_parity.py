@@ -101,7 +101,7 @@ def _class_samples(mol, per_class=2, seed=0):
     return [q for v in by.values() for q in v]
 
 
-@pytest.mark.parametrize("basis", ["A", "B"])
+@pytest.mark.parametrize("basis", ["A", "B", "C"])
 def test_eri_blocks(jkmod, basis):
     wl = synth.small_workload(2, basis, seed=21)
     say("eri blocks", basis, wl.mol.nshell)
@@ -112,15 +112,30 @@ def test_eri_blocks(jkmod, basis):
         err = np.abs(got - ref).max()
         assert err <= 1e-12 * max(1.0, np.abs(ref).max()), (q, err)
         got32 = plan.eri_block(*q, precision="fp32")
-        assert np.abs(got32 - ref).max() <= 2e-5 * max(1e-3, np.abs(ref).max()), q
+        # single precision: the horizontal transfers over |A - B| of several
+        # bohr lose more digits with f and g shells on both centres (basis C:
+        # (ff|pp) between waters reaches 2e-4 relative)
+        tol32 = 5e-4 if basis == "C" else 2e-5
+        assert np.abs(got32 - ref).max() <= tol32 * max(1e-3, np.abs(ref).max()), q
 
 
-@pytest.mark.parametrize("basis", ["A", "B"])
+@pytest.mark.parametrize("basis", ["A", "B", "C"])
 def test_schwarz(jkmod, basis):
     wl = synth.small_workload(3, basis, seed=5)
     say("schwarz", basis)
     plan = jkmod.Plan(wl.mol)
-    np.testing.assert_allclose(plan.schwarz(), o.schwarz(wl.mol), rtol=1e-12, atol=1e-300)
+    got, ref = plan.schwarz(), o.schwarz(wl.mol)
+    if basis == "C":
+        # Q^2 is a largest diagonal integral: the bar of the integral blocks
+        # (1e-12 of the block's scale) applies to it.  With g shells on both
+        # centres the horizontal transfers (and the oracle's Hermite
+        # expansions) cancel several digits in the small distant-pair
+        # integrals, so Q itself is not held to 1e-12 relative there.
+        err = np.abs(got ** 2 - ref ** 2).max()
+        assert err <= 1e-12 * max(1.0, float((ref ** 2).max())), err
+        np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-300)
+    else:
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-300)
 
 
 # ---------------------------------------------------------------------------
@@ -140,7 +155,8 @@ def test_jk_c0(jkmod, torch_cuda):
 
 
 @pytest.mark.parametrize("basis,nw,nset,cut", [("B", 2, 2, 1e-13), ("A", 5, 1, 1e-10), ("B", 3, 3, 1e-13), ("A", 1, 1, 0.0),
-                                               ("A", 8, 1, 1e-13), ("B", 6, 2, 1e-13)])
+                                               ("A", 8, 1, 1e-13), ("B", 6, 2, 1e-13), ("C", 1, 2, 1e-13),
+                                               ("C", 2, 1, 1e-13)])
 def test_jk_small(jkmod, torch_cuda, basis, nw, nset, cut):
     wl = synth.small_workload(nw, basis, seed=40 + nw, nset=nset)
     wl.cutoff = cut
@@ -221,7 +237,7 @@ def test_density_screening(jkmod, torch_cuda, basis, nw, thr):
 # ---------------------------------------------------------------------------
 # mixed precision
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("basis,nw", [("A", 4), ("B", 4), ("A", 8)])
+@pytest.mark.parametrize("basis,nw", [("A", 4), ("B", 4), ("A", 8), ("C", 2)])
 def test_mixed_small(jkmod, torch_cuda, basis, nw):
     wl = synth.small_workload(nw, basis, seed=77)
     say("mixed", basis)
@@ -356,7 +372,7 @@ def test_full_size_sampled(jkmod, torch_cuda, name):
 # ---------------------------------------------------------------------------
 # every kernel family and row setting, not only the tuned ones
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("basis,nw", [("B", 6), ("A", 8)])
+@pytest.mark.parametrize("basis,nw", [("B", 6), ("A", 8), ("C", 1)])
 def test_forced_families(jkmod, torch_cuda, basis, nw):
     """Each class forced to family 1, 2, then 3 (where built), with row mode
     for long bras, off, and for every bra, in FP64 and mixed precision,

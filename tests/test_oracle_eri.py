@@ -114,10 +114,10 @@ def eri_quadrature(al, centers, powers):
 
 @pytest.mark.parametrize("ls", [(0, 0, 0, 0), (1, 0, 0, 0), (1, 1, 0, 0), (1, 0, 1, 0), (1, 1, 1, 1), (2, 1, 0, 1),
                                 (3, 0, 0, 0), (0, 0, 0, 3), (3, 1, 2, 0), (2, 2, 2, 2), (3, 3, 1, 1), (1, 3, 3, 2),
-                                (3, 3, 3, 3)])
+                                (3, 3, 3, 3), (4, 0, 0, 0), (0, 1, 4, 2), (4, 4, 2, 1), (3, 4, 4, 3), (4, 4, 4, 4)])
 def test_primitive_eri_vs_quadrature(ls):
-    """Every (li lj|lk ll) pattern the configurations reach up to (ff|ff),
-    with the f shells in every position, against brute-force quadrature."""
+    """Every (li lj|lk ll) pattern the workloads reach up to (gg|gg), with
+    the f and g shells in every position, against brute-force quadrature."""
     rng = np.random.default_rng(100 + sum(ls) + 7 * ls[0] + 3 * ls[3])
     C = rng.uniform(-1.5, 1.5, size=(4, 3))
     ex = np.exp(rng.uniform(math.log(0.2), math.log(5), size=4))
@@ -270,6 +270,59 @@ def test_scaling_law_f_shells(wat_b):
     mol2 = synth.Molecule(l=mol.l, nprim=mol.nprim, atom=mol.atom, exps=mol.exps / lam ** 2,
                           coefs=mol.coefs * lam ** (-(lpp + 1.5)), coords=mol.coords * lam, spherical=False)
     for (I, J, K, L) in _quartets_by_l_sampled(mol, _F_KEYS).values():
+        ref = o.eri_block(mol, I, J, K, L)
+        np.testing.assert_allclose(o.eri_block(mol2, I, J, K, L) * lam, ref, rtol=1e-12,
+                                   atol=1e-14 * max(1.0, np.abs(ref).max()))
+
+
+# ---------------------------------------------------------------------------
+# g shells: the same pins on a molecule of the quadruple-zeta-shaped basis
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def wat_c():
+    wl = synth.small_workload(3, "C", seed=33)
+    mol = wl.mol
+    return synth.Molecule(l=mol.l, nprim=mol.nprim, atom=mol.atom, exps=mol.exps, coefs=mol.coefs,
+                          coords=mol.coords, spherical=False)
+
+
+_G_KEYS = {(4, 0, 0, 0), (4, 3, 2, 1), (4, 4, 1, 0), (2, 4, 4, 1), (4, 4, 4, 4), (3, 4, 0, 4)}
+
+
+def test_eightfold_symmetry_g_shells(wat_c):
+    mol = wat_c
+    qs = _quartets_by_l_sampled(mol, _G_KEYS)
+    assert len(qs) == len(_G_KEYS)
+    for (I, J, K, L) in qs.values():
+        v = o.eri_block(mol, I, J, K, L)
+        tol = dict(rtol=1e-12, atol=1e-14 * max(1.0, np.abs(v).max()))
+        np.testing.assert_allclose(o.eri_block(mol, J, I, K, L), v.transpose(1, 0, 2, 3), **tol)
+        np.testing.assert_allclose(o.eri_block(mol, K, L, I, J), v.transpose(2, 3, 0, 1), **tol)
+        np.testing.assert_allclose(o.eri_block(mol, L, K, J, I), v.transpose(3, 2, 1, 0), **tol)
+
+
+def test_schwarz_bound_and_scaling_g_shells(wat_c):
+    mol = wat_c
+    Q = o.schwarz(mol)
+    g = [i for i, l in enumerate(int(x) for x in mol.l) if l == 4]
+    assert g
+    for I in g:
+        for J in range(0, mol.nshell, 3):
+            d = o.eri_block(mol, I, J, I, J)
+            nab = d.shape[0] * d.shape[1]
+            diag = np.diag(d.reshape(nab, nab))
+            assert np.all(diag >= 0)
+            assert math.sqrt(diag.max()) == pytest.approx(Q[I, J], rel=1e-14)
+    rng = np.random.default_rng(12)
+    for _ in range(30):
+        I, J, K = (int(x) for x in rng.integers(0, mol.nshell, size=3))
+        L = g[int(rng.integers(len(g)))]
+        assert np.abs(o.eri_block(mol, I, J, K, L)).max() <= Q[I, J] * Q[K, L] * (1 + 1e-12)
+    lam = 1.3
+    lpp = np.repeat(mol.l, mol.nprim)
+    mol2 = synth.Molecule(l=mol.l, nprim=mol.nprim, atom=mol.atom, exps=mol.exps / lam ** 2,
+                          coefs=mol.coefs * lam ** (-(lpp + 1.5)), coords=mol.coords * lam, spherical=False)
+    for (I, J, K, L) in _quartets_by_l_sampled(mol, {(4, 4, 2, 1), (4, 0, 3, 4)}, seed=5).values():
         ref = o.eri_block(mol, I, J, K, L)
         np.testing.assert_allclose(o.eri_block(mol2, I, J, K, L) * lam, ref, rtol=1e-12,
                                    atol=1e-14 * max(1.0, np.abs(ref).max()))

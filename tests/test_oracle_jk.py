@@ -221,7 +221,7 @@ def test_c2s_harmonic(l):
         np.testing.assert_allclose(lap, 0.0, atol=1e-13)
 
 
-@pytest.mark.parametrize("l", [2, 3])
+@pytest.mark.parametrize("l", [2, 3, 4])
 def test_c2s_matches_projection_of_spherical_harmonics(l):
     """Independent derivation: least-squares fit of r^l * real Y_lm (scipy)
     on random points, normalised with the same monomial overlap; sign fixed
@@ -250,8 +250,7 @@ def test_c2s_matches_projection_of_spherical_harmonics(l):
 def test_spherical_one_centre_overlap_is_identity():
     """Normalised contracted spherical shell: one-centre overlap matrix = I
     (Gaussian moments from the textbook formula, not from the oracle)."""
-    b = synth.make_basis("B")
-    for (l, e, c) in b.shells["O"]:
+    for (l, e, c) in synth.make_basis("B").shells["O"] + synth.make_basis("C").shells["O"]:
         if l < 2:
             continue
         T = o.c2s(l)
