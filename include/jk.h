@@ -141,6 +141,27 @@ int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int3
                double mix_threshold, double omega, double *J, double *K, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * build as jk_execute, with the same arguments and results, but its scratch
+ * (Cartesian J', K' and density, the pair-ordered J' buffer, the block
+ * maxima, the counters) taken from one fixed device array of
+ * JK_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from load until
+ * the process ends.  Calls no allocating routine.  A build that needs more
+ * scratch than the array holds (8 bytes x (nset nao_cart^2 (2 + spherical)
+ * + nset x the pair-block elements + nshell^2) + 64 x classes, each part
+ * rounded to 256 bytes) returns JK_EINVAL before anything runs.  Every
+ * call on one GPU shares that GPU's array and leaves its contents there:
+ * calls that overlap on one GPU race (order them on one stream), and
+ * jk_plan_stats after such a call reads the counters the last call on that
+ * GPU wrote.  Each call clears what it accumulates into.  Per-kernel
+ * profiling (jk_plan_profile) does not apply to it.
+ */
+#define JK_NOALLOC_SCRATCH_BYTES (128u << 20)
+int jk_execute_noalloc(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int32_t precision,
+                       double mix_threshold, double omega, double *J, double *K, void *stream);
+
+/*
  * Density screening for direct SCF (Section 2: the screening of the J and K
  * changes by the density change, at shell-pair level).  With threshold > 0,
  * later jk_execute calls on this plan drop every quartet with

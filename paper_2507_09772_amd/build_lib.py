@@ -131,6 +131,7 @@ def build(jobs: int | None = None, extra=(), verbose=False, incremental=False, r
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     jobs = jobs or min(16, os.cpu_count() or 4)
     units = [("jk_api", os.path.join(CSRC, "jk_api.hip"), []), ("jk_batch", os.path.join(CSRC, "jk_batch.hip"), []),
+             ("jk_noalloc", os.path.join(CSRC, "jk_noalloc.hip"), []),
              ("kern_persist", os.path.join(CSRC, "kern_persist.hip"), [])]
     for (i, j) in BRAS:
         units.append((f"kern_{i}{j}", os.path.join(CSRC, "kern_bra.hip"), [f"-DJK_LI={i}", f"-DJK_LJ={j}"]))
