@@ -410,13 +410,14 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
             if (g.kind == 1) d.a.row_pos = b->d_tasks + d.pad[2];
         }
     }
-    // persistent form (JK_BATCH_PERSIST, default on): the family-1 row tasks of
-    // the one- and two-root classes leave their per-class launches for one
-    // queue per precision, ordered by work per task (heaviest first)
+    // persistent form (JK_BATCH_PERSIST=1; off by default: measured slower
+    // than the per-class launches on parallel branches): the family-1 row
+    // tasks of the one- and two-root classes leave their per-class launches
+    // for one queue per precision, ordered by work per task (heaviest first)
     std::vector<std::vector<std::pair<double, std::pair<int32_t, int32_t>>>> pitems(2);
     {
         const char *pe = getenv("JK_BATCH_PERSIST");
-        const bool on = !(pe && pe[0] == '0');
+        const bool on = pe && pe[0] == '1';
         std::vector<Group> keep;
         for (const Group &g : b->groups) {
             const int li = g.cid / 125, lj = (g.cid / 25) % 5, lk = (g.cid / 5) % 5, ll = g.cid % 5;

@@ -1160,7 +1160,19 @@ struct K2Cfg {
     static constexpr int RB = (QW * C::NR * 3 * C::S * 8 <= 48 * 1024) ? C::NR
                               : ((48 * 1024) / (QW * 3 * C::S * 8) > 0 ? (48 * 1024) / (QW * 3 * C::S * 8) : 1);
     static constexpr int NRB = (C::NR + RB - 1) / RB;
-    static constexpr int TAB = RB * 3 * C::S;                 // 2-D table entries per quartet
+    // primitive quartets whose tables are built at once: enough that every
+    // lane of a quartet's group has a (primitive, root, direction) task,
+    // within 24 KB of tables per wave (in FP64); one where the roots come in
+    // blocks
+    static constexpr int pb_() {
+        if (NRB > 1) return 1;
+        int pb = LPQ / (3 * C::NR);
+        const int cap = (24 * 1024) / (QW * C::NR * 3 * C::S * 8);
+        if (pb > cap) pb = cap;
+        return pb < 1 ? 1 : pb;
+    }
+    static constexpr int PB = pb_();
+    static constexpr int TAB = PB * RB * 3 * C::S;            // 2-D table entries per quartet
     // LDS digestion blocks: jij, jkl, kik, kil, kjk, kjl
     static constexpr int O_JIJ = 0;
     static constexpr int O_JKL = O_JIJ + C::NI * C::NJ;
@@ -1181,6 +1193,9 @@ struct K2Cfg {
 };
 
 // One wave handles QW quartets with its own tables and digestion blocks;
+// the tables of PB primitive quartets are built at once (every lane of a
+// quartet's group takes a (primitive, root, direction) task) and then
+// consumed one after another;
 // all synchronisation inside is per wave, so the waves of a workgroup are
 // independent.  ROW: the four K blocks and J_IJ go to the
 // workgroup's shared K rows of the (uniform) bra instead (row mode), only
@@ -1191,7 +1206,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
     using C = Cls<LI, LJ, LK, LL>;
     using F = K2Cfg<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, S = C::S;
-    constexpr int QW = F::QW, LPQ = F::LPQ, SPL = F::SPL, CB = F::CB, NPASS = F::NPASS;
+    constexpr int QW = F::QW, LPQ = F::LPQ, SPL = F::SPL, CB = F::CB, NPASS = F::NPASS, PB = F::PB;
     const int lane = lane_index();
     const int q = QW > 1 ? lane / LPQ : 0;
     const int sl = QW > 1 ? lane % LPQ : lane;
@@ -1245,26 +1260,31 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
 #pragma unroll
                 for (int d = 0; d < NL; ++d) acc[k][bb][d] = (R)0;
 
-        // every primitive quartet once per operator variant
+        // every primitive quartet once per operator variant, PB of them per
+        // table build
         const int vb = variant_begin(a.omega), nv = variant_end(a.omega) - vb;
-        for (int it = 0; it < npq_max * nv; ++it) {
-            const int ipq = it / nv, var = vb + it % nv;
-            const bool has = ipq < npq;
-            const int ib = has ? ipq % npb : 0, ik = has ? ipq / npb : 0;
+        const int nit = npq_max * nv;
+        for (int it0 = 0; it0 < nit; it0 += PB) {
             // with a single table set per quartet the tables of pass 0 are
             // reused by the later passes
-            const bool build = pass == 0 || npq_max * nv > 1 || F::NRB > 1;
+            const bool build = pass == 0 || nit > PB || F::NRB > 1;
 #pragma unroll
             for (int rb = 0; rb < F::NRB; ++rb) {
             constexpr int RB = F::RB;
             const int r0 = rb * RB, nrb = NR - r0 < RB ? NR - r0 : RB;  // roots of this block
             if (build) {
                 wave_sync();
-                const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
-                const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
-                const PQuart<R> g = prim_quartet<R>(pb, pk);
-                for (int t = sl; t < 3 * nrb && lane_used; t += LPQ) {
-                    const int rl = t / 3, r = r0 + rl, x = t % 3;
+                // one task per (primitive quartet of the batch, root, direction)
+                for (int t = sl; t < PB * 3 * nrb && lane_used; t += LPQ) {
+                    const int p = t / (3 * nrb), t2 = t - p * (3 * nrb);
+                    const int it = it0 + p;
+                    const int ipq = it / nv, var = vb + it % nv;
+                    const bool has = it < nit && ipq < npq;
+                    const int ib = has ? ipq % npb : 0, ik = has ? ipq / npb : 0;
+                    const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
+                    const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
+                    const PQuart<R> g = prim_quartet<R>(pb, pk);
+                    const int rl = t2 / 3, r = r0 + rl, x = t2 % 3;
                     R u, w;
                     rys_root1_op<NR, R>(g.T, g.rho, a.omega, var, r, a.tab, u, w);
                     const R b00 = (R)0.5 * u * g.rpq;
@@ -1280,16 +1300,18 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                     const R c00 = pax - g.fq * u * pqx;
                     const R c00p = qcx + g.fp * u * pqx;
                     const R sc2 = x == 2 ? (has ? w * g.pref : (R)0) : (R)1;
-                    R *dst = tq + (rl * 3 + x) * S;
+                    R *dst = tq + ((p * RB + rl) * 3 + x) * S;
                     rys2d<LI, LJ, LK, LL, R>(c00, c00p, b00, b10, b01, abx, cdx, sc2,
                                              [&](int ia, int ib2, int ic, int id, R v) { dst[F::tix(ia, ib2, ic, id)] = v; });
                 }
                 wave_sync();
             }
+            for (int p = 0; p < PB; ++p) {
+            if (it0 + p >= nit) break;  // uniform in the wave
 #pragma unroll
             for (int rl = 0; rl < RB; ++rl) {
                 if (r0 + rl >= NR) continue;
-                const R *tr = tq + rl * 3 * S;
+                const R *tr = tq + (p * RB + rl) * 3 * S;
 #pragma unroll
                 for (int k = 0; k < SPL; ++k) {
 #pragma unroll
@@ -1306,6 +1328,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                     }
                 }
             }
+            }  // primitive quartet of the batch
             }  // root block
         }
 
@@ -1370,11 +1393,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                             kik += v * djl;
                             kil[d] += v * djk;
                             kjk += v * dil[d];
-                            if constexpr (ROW) {
-                                if (a.do_k) atomicAdd(&rJ[b * ncols + cL + d], wq * v * dik);
-                            } else {
-                                kjlp[bb][d] += v * dik;
-                            }
+                            kjlp[bb][d] += v * dik;
                         }
                         if (a.do_j) atomicAdd(ROW ? &rjij[ia * NJ + b] : &dq[F::O_JIJ + ia * NJ + b], 2.0 * wq * jij);
                         if (a.do_k) atomicAdd(ROW ? &rJ[b * ncols + cK + ic] : &dq[F::O_KJK + b * NK + ic], wq * kjk);
@@ -1386,21 +1405,30 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                     }
                     if (a.do_k) atomicAdd(ROW ? &rI[ia * ncols + cK + ic] : &dq[F::O_KIK + ia * NK + ic], wq * kik);
                 }
-                if constexpr (!ROW) {
-                    // K_JL of each quartet: sum of its lanes' partials
-                    if (a.do_k) {
-                        double *part = dig + QW * F::DIG;
+                // K_JL of each quartet: the sum of its lanes' partials (every
+                // slot of the quartet adds to the same elements), reduced
+                // through LDS without atomics; in row mode one LDS atomic per
+                // element then adds it to the bra's K row, at the quartet's
+                // ket column (kept in the quartet's unused K_JL digestion slot)
+                if (a.do_k) {
+                    double *part = dig + QW * F::DIG;
+                    if constexpr (ROW) {
+                        if (lane_used && sl == 0) dq[F::O_KJL] = (double)cL;
+                    }
 #pragma unroll
-                        for (int bb = 0; bb < CB; ++bb)
+                    for (int bb = 0; bb < CB; ++bb)
 #pragma unroll
-                            for (int d = 0; d < NL; ++d) part[lane * (CB * NL) + bb * NL + d] = wq * kjlp[bb][d];
-                        wave_sync();
-                        for (int t = lane; t < QW * CB * NL; t += 64) {
-                            const int q2 = t / (CB * NL), bd = t % (CB * NL);
-                            const int b = pass * CB + bd / NL;
-                            if (b >= NJ) continue;
-                            double sum = 0.0;
-                            for (int l2 = 0; l2 < LPQ; ++l2) sum += part[(q2 * LPQ + l2) * (CB * NL) + bd];
+                        for (int d = 0; d < NL; ++d) part[lane * (CB * NL) + bb * NL + d] = wq * kjlp[bb][d];
+                    wave_sync();
+                    for (int t = lane; t < QW * CB * NL; t += 64) {
+                        const int q2 = t / (CB * NL), bd = t % (CB * NL);
+                        const int b = pass * CB + bd / NL;
+                        if (b >= NJ) continue;
+                        double sum = 0.0;
+                        for (int l2 = 0; l2 < LPQ; ++l2) sum += part[(q2 * LPQ + l2) * (CB * NL) + bd];
+                        if constexpr (ROW) {
+                            if (sum != 0.0) atomicAdd(&rJ[b * ncols + (int)dig[q2 * F::DIG + F::O_KJL] + bd % NL], sum);
+                        } else {
                             dig[q2 * F::DIG + F::O_KJL + b * NL + bd % NL] = sum;
                         }
                     }
@@ -1591,13 +1619,22 @@ struct K3Cfg {
     static constexpr int QW = 64 / LPQ;               // quartets per wave
     static constexpr int NV = C::NJ * C::NK * C::NL;  // accumulators per lane
     static constexpr int TS = (LJ + 1) * (LK + 1) * (LL + 1);  // per-lane table per direction
-    // per wave, in R: roots [QW][NR][2], then G [QW][NR][3][GS]
-    static constexpr int RW = QW * C::NR * 2;
-    static constexpr int GW = QW * C::NR * 3 * GS;
+    // primitive quartets whose tables are built at once: enough that most
+    // lanes of a quartet's group have a (primitive, root) task, within
+    // 20 KB of tables per wave (in FP64)
+    static constexpr int pb_() {
+        int pb = LPQ / C::NR;
+        const int cap = (20 * 1024) / (QW * C::NR * 3 * GS * 8);
+        if (pb > cap) pb = cap;
+        return pb < 1 ? 1 : pb;
+    }
+    static constexpr int PB = pb_();
+    // per wave, in R: G [QW][PB][NR][3][GS]
+    static constexpr int GW = QW * PB * C::NR * 3 * GS;
     // per wave, doubles: J'_KL of the wave's quartets [QW][NK NL]
     static constexpr int JW = QW * C::NK * C::NL;
     template <typename R>
-    static constexpr size_t wave_bytes() { return (size_t)JW * sizeof(double) + (size_t)(RW + GW) * sizeof(R); }
+    static constexpr size_t wave_bytes() { return (size_t)JW * sizeof(double) + (size_t)GW * sizeof(R); }
     static constexpr size_t per_set(int ncols) {
         return sizeof(double) * ((size_t)(C::NI + C::NJ) * ncols + (size_t)C::NI * C::NJ);
     }
@@ -1667,7 +1704,7 @@ __global__ void __launch_bounds__(NT) jk_k3_row(const JkArgs a_in, const BatchDe
     using C = Cls<LI, LJ, LK, LL>;
     using F = K3Cfg<LI, LJ, LK, LL>;
     constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, NAB = C::NAB;
-    constexpr int LPQ = F::LPQ, QW = F::QW, NW = NT / 64, NCC = F::NCC, TS = F::TS;
+    constexpr int LPQ = F::LPQ, QW = F::QW, NW = NT / 64, NCC = F::NCC, TS = F::TS, PB = F::PB;
     extern __shared__ double smem3[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_index();
     int task = blockIdx.x;
@@ -1682,8 +1719,7 @@ __global__ void __launch_bounds__(NT) jk_k3_row(const JkArgs a_in, const BatchDe
     const int per_set = (NI + NJ) * ncols + NAB;
     double *rows = smem3;
     double *jkl = rows + (size_t)per_set * a.nset + (size_t)wave * F::JW;
-    R *rt = (R *)(rows + (size_t)per_set * a.nset + (size_t)NW * F::JW) + (size_t)wave * (F::RW + F::GW);
-    R *gt = rt + F::RW;
+    R *gt = (R *)(rows + (size_t)per_set * a.nset + (size_t)NW * F::JW) + (size_t)wave * F::GW;
     const int i = a.row_pos[3 * task];
     const int jbeg = a.row_pos[3 * task + 1], cnt = a.row_pos[3 * task + 2];
     const int bra = a.bra_list[i];
@@ -1721,58 +1757,56 @@ __global__ void __launch_bounds__(NT) jk_k3_row(const JkArgs a_in, const BatchDe
 #pragma unroll
         for (int e = 0; e < F::NV; ++e) V[e] = (R)0;
         const int vb = variant_begin(a.omega), nvar = variant_end(a.omega) - vb;
-        for (int ik = 0; ik < a.npk; ++ik) {
-            const PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
-            for (int ib = 0; ib < a.npb; ++ib) {
-                const PrimPair pb = a.pp[B.pp_off + ib * B.pp_stride];
-                const PQuart<R> g = prim_quartet<R>(pb, pk);
-                for (int var = vb; var < vb + nvar; ++var) {
-                    R *rq = rt + qq * (NR * 2);
-                    R *gq = gt + qq * (NR * 3 * F::GS);
-                    wave_sync();
-                    // roots and weights, one lane per root
-                    if (lane_used && ia < NR) {
-                        R u, w;
-                        rys_root1_op<NR, R>(g.T, g.rho, a.omega, var, ia, a.tab, u, w);
-                        rq[2 * ia] = u;
-                        rq[2 * ia + 1] = w * g.pref;
-                    }
-                    wave_sync();
-                    // vertical recurrence tables, one lane per (root, direction)
-                    for (int t = ia; t < 3 * NR && lane_used; t += LPQ) {
-                        const int r = t / 3, x = t % 3;
-                        const R u = rq[2 * r];
-                        const R b00 = (R)0.5 * u * g.rpq;
-                        const R b10 = g.hb * ((R)1 - g.fq * u);
-                        const R b01 = g.hk * ((R)1 - g.fp * u);
-                        const R pqx = sel3(x, g.PQ[0], g.PQ[1], g.PQ[2]);
-                        const R pax = sel3(x, g.PA[0], g.PA[1], g.PA[2]);
-                        const R qcx = sel3(x, g.QC[0], g.QC[1], g.QC[2]);
-                        const R c00 = pax - g.fq * u * pqx;
-                        const R c00p = qcx + g.fp * u * pqx;
-                        const R s = x == 2 ? rq[2 * r + 1] : (R)1;
-                        vrr2d<F::NA, NCC, R>(c00, c00p, b00, b10, b01, s, gq + (r * 3 + x) * F::GS);
-                    }
-                    wave_sync();
-                    // this lane's rows, transfers and elements, root by root
+        const int nit = a.npb * a.npk * nvar;
+        R *gq = gt + qq * (PB * NR * 3 * F::GS);
+        for (int it0 = 0; it0 < nit; it0 += PB) {
+            wave_sync();
+            // one lane per (primitive quartet of the batch, root): the root
+            // and weight, then the vertical recurrence tables of the three
+            // directions
+            for (int t = ia; t < PB * NR && lane_used; t += LPQ) {
+                const int p = t / NR, r = t - p * NR;
+                const int it = it0 + p;
+                if (it >= nit) break;
+                const int ipq = it / nvar, var = vb + it % nvar;
+                const int ib = ipq % a.npb, ik = ipq / a.npb;
+                const PQuart<R> g = prim_quartet<R>(a.pp[B.pp_off + ib * B.pp_stride], a.pp[Kt.pp_off + ik * Kt.pp_stride]);
+                R u, w;
+                rys_root1_op<NR, R>(g.T, g.rho, a.omega, var, r, a.tab, u, w);
+                const R b00 = (R)0.5 * u * g.rpq;
+                const R b10 = g.hb * ((R)1 - g.fq * u);
+                const R b01 = g.hk * ((R)1 - g.fp * u);
+                R *dst = gq + (p * NR + r) * 3 * F::GS;
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        R T[3][TS];
+                for (int x = 0; x < 3; ++x) {
+                    const R c00 = g.PA[x] - g.fq * u * g.PQ[x];
+                    const R c00p = g.QC[x] + g.fp * u * g.PQ[x];
+                    vrr2d<F::NA, NCC, R>(c00, c00p, b00, b10, b01, x == 2 ? w * g.pref : (R)1, dst + x * F::GS);
+                }
+            }
+            wave_sync();
+            // this lane's rows, transfers and elements, primitive quartet by
+            // primitive quartet and root by root
+            for (int p = 0; p < PB; ++p) {
+                if (it0 + p >= nit) break;  // uniform in the wave
+                const R *gp = gq + p * NR * 3 * F::GS;
 #pragma unroll
-                        for (int x = 0; x < 3; ++x)
-                            hrr_lane<LJ, LK, LL, R>(gq + (r * 3 + x) * F::GS + ae[x] * (NCC + 1), ab[x], cd[x], T[x]);
+                for (int r = 0; r < NR; ++r) {
+                    R T[3][TS];
 #pragma unroll
-                        for (int b = 0; b < NJ; ++b)
+                    for (int x = 0; x < 3; ++x)
+                        hrr_lane<LJ, LK, LL, R>(gp + (r * 3 + x) * F::GS + ae[x] * (NCC + 1), ab[x], cd[x], T[x]);
 #pragma unroll
-                            for (int c = 0; c < NK; ++c)
+                    for (int b = 0; b < NJ; ++b)
 #pragma unroll
-                                for (int d = 0; d < NL; ++d) {
-                                    const int ix = (cart_comp(LJ, b, 0) * (LK + 1) + cart_comp(LK, c, 0)) * (LL + 1) + cart_comp(LL, d, 0);
-                                    const int iy = (cart_comp(LJ, b, 1) * (LK + 1) + cart_comp(LK, c, 1)) * (LL + 1) + cart_comp(LL, d, 1);
-                                    const int iz = (cart_comp(LJ, b, 2) * (LK + 1) + cart_comp(LK, c, 2)) * (LL + 1) + cart_comp(LL, d, 2);
-                                    V[(b * NK + c) * NL + d] += T[0][ix] * T[1][iy] * T[2][iz];
-                                }
-                    }
+                        for (int c = 0; c < NK; ++c)
+#pragma unroll
+                            for (int d = 0; d < NL; ++d) {
+                                const int ix = (cart_comp(LJ, b, 0) * (LK + 1) + cart_comp(LK, c, 0)) * (LL + 1) + cart_comp(LL, d, 0);
+                                const int iy = (cart_comp(LJ, b, 1) * (LK + 1) + cart_comp(LK, c, 1)) * (LL + 1) + cart_comp(LL, d, 1);
+                                const int iz = (cart_comp(LJ, b, 2) * (LK + 1) + cart_comp(LK, c, 2)) * (LL + 1) + cart_comp(LL, d, 2);
+                                V[(b * NK + c) * NL + d] += T[0][ix] * T[1][iy] * T[2][iz];
+                            }
                 }
             }
         }

@@ -45,7 +45,17 @@ def _singles(torch, plans, Ds, precision):
     return [(J.cpu().numpy(), K.cpu().numpy()) for J, K in out]
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-11), ("fp32", 1e-9)])
+# Single precision: the batch runs the short bras of a class as 64-lane row
+# tasks where the single build runs tiles of another family, and the FP32
+# rounding of one quartet's elements differs between kernels by ~1e-7
+# relative.  Mixed: FP32 quartets have bounds below 1e-4, so an element of J
+# or K built from many of them differs by up to ~1e-10 between the two;
+# all-FP32: elements of order one differ by up to ~1e-8.
+MIXED_TOL = 1e-9
+FP32_TOL = 1e-7
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", MIXED_TOL), ("fp32", FP32_TOL)])
 def test_batch_matches_single_and_replays(env, precision, tol):
     torch, jk = env
     wls = synth.batch_workload(nmol=24, nset=2, seed=11)
@@ -74,14 +84,19 @@ def test_batch_matches_single_and_replays(env, precision, tol):
     b.close()
 
 
-@pytest.mark.parametrize("fam", [1, 2])
-def test_batch_row_tasks(env, fam):
+@pytest.mark.parametrize("fam,persist,branches", [(1, "0", "4"), (1, "1", "4"), (1, "1", "1"), (2, "0", "1")])
+def test_batch_row_tasks(env, fam, persist, branches):
     """Every class forced to row mode on all bras (the batch then runs row
     tasks instead of tiles) and to one family, FP64 and mixed, against the
-    single-molecule builds and the oracle."""
+    single-molecule builds and the oracle; with family 1 also in the
+    persistent form (one work queue for the one- and two-root classes) and
+    on one or four graph branches."""
     torch, jk = env
     wls = synth.batch_workload(nmol=12, nset=2, seed=13)
-    say("batch rows", fam, [w.mol.nwater for w in wls])
+    say("batch rows", fam, persist, branches, [w.mol.nwater for w in wls])
+    saved = {k: os.environ.get(k) for k in ("JK_BATCH_PERSIST", "JK_BATCH_BRANCHES")}
+    os.environ["JK_BATCH_PERSIST"] = persist
+    os.environ["JK_BATCH_BRANCHES"] = branches
     try:
         for c in jk.canonical_classes():
             for p in ("fp64", "fp32"):
@@ -89,7 +104,7 @@ def test_batch_row_tasks(env, fam):
                 jk.tune_set(*c, p, fam if avail & fam else 0)
                 jk.tune_set_row(*c, p, 3)
         plans, Ds = _setup(torch, jk, wls)
-        for precision, tol in (("fp64", 1e-12), ("mixed", 1e-11)):
+        for precision, tol in (("fp64", 1e-12), ("mixed", MIXED_TOL)):
             ref = _singles(torch, plans, Ds, precision)
             b = jk.Batch(plans, nset=2, precision=precision)
             Js = [torch.full_like(D, np.nan) for D in Ds]
@@ -106,6 +121,11 @@ def test_batch_row_tasks(env, fam):
                 J0, K0, _ = o.jk(w.mol, w.D, w.cutoff, mode=1)
                 assert np.abs(ref[m][0] - J0).max() <= 1e-6  # mixed reference vs FP64 oracle
     finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
         for c in jk.canonical_classes():
             for p in ("fp64", "fp32"):
                 jk.tune_set(*c, p, 0)
