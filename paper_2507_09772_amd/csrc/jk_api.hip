@@ -297,6 +297,8 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
     {
         const char *nr = getenv("JK_NO_ROW");
         P->no_row = nr && nr[0] == '1';
+        const char *nd = getenv("JK_NO_DSTAGE");
+        P->no_dstage = nd && nd[0] == '1';
     }
     const int ns = P->ns = basis->nshell;
     P->natom = basis->natom;
@@ -986,6 +988,7 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
         for (int pass = 0; pass < npass; ++pass) {
             const int pr = precision == JK_MIXED ? (pass == 0 ? 1 : 0) : (precision == JK_FP32 ? 1 : 0);
             a.sel = precision == JK_MIXED ? (pass == 0 ? SEL_LO : SEL_HI) : SEL_ALL;
+            a.dstage = 0;
             const int f = c.fam[pr];
             // tiles (the short rest) of family 3 classes run in the fallback family
             const int ft = f == 3 ? tile_fallback(c.li, c.lj, c.lk, c.ll) : f;
@@ -1011,15 +1014,22 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
                 a.seg_same = c.seg_same;
             }
             if (longrows) {
-                // long bras: 256-lane workgroups over chunks of their kets
+                // long bras: 256-lane workgroups over chunks of their kets;
+                // family 1 stages the bra's D rows in LDS where the
+                // workgroup's LDS stays within DSTAGE_LDS_MAX
                 a.row_pos = c.d_rowc[f - 1];
                 a.nrow = c.nrowc[f - 1];
+                a.dstage = f == 1 && k1_dstage_class(c.li, c.lj) && !P->no_dstage &&
+                           row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4, c.npb) +
+                                   sizeof(double) * (size_t)nset * (ncart(c.li) + ncart(c.lj)) * ncols <=
+                               (size_t)DSTAGE_LDS_MAX;
                 set_count(slot + 1, c.nq_row);
                 if ((rc = mark(slot + 1))) return rc;
                 HIPCHK(e.row[f - 1][pr](a, s));
             }
             if (shortrows) {
                 // short bras: one 64-lane workgroup each
+                a.dstage = 0;
                 a.row_pos = c.d_srowt;
                 a.nrow = c.nsrow;
                 set_count(slot + 3, c.nq - c.nq_row);

@@ -69,6 +69,9 @@ JK_HD constexpr bool has_family3(int li, int lj, int lk, int ll) {
     return li >= 1 && ncart(lj) * ncart(lk) * ncart(ll) <= 64 && ncart4(li, lj, lk, ll) >= 27;
 }
 JK_HD constexpr int k3_qw(int li) { return 64 / ncart(li); }
+// Family-1 row kernels that can stage the bra's D rows in LDS: the small
+// bras, whose rows fit the staging budget on molecules of interest.
+JK_HD constexpr bool k1_dstage_class(int li, int lj) { return ncart(li) + ncart(lj) <= 7; }
 JK_HD constexpr int tile_fallback(int li, int lj, int lk, int ll) { return has_family2(li, lj, lk, ll) ? 2 : 1; }
 // Family 2: lanes per quartet = ncart(li) * ncart(lk) (slot = (a, c)).
 JK_HD constexpr int k2_slots(int li, int lj, int lk, int ll) { return ncart(li) * ncart(lk); }
@@ -133,6 +136,10 @@ struct JkArgs {
     int32_t nrow;
     const int32_t *tpos, *tshK, *tshL, *aoc;
     int32_t ncolK, ncolL, seg_same;
+    // family-1 row mode: the bra's rows of D over the same compressed
+    // columns are staged in LDS once per task (1), so the exchange digestion
+    // reads them there instead of four scattered global loads per element
+    int32_t dstage;
     // densities and results (Cartesian, [nset][nao][nao])
     const double *D;
     double *J, *K;

@@ -965,10 +965,27 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
     // the bra's primitive pair records, then the rows
     PrimPair *sbra = reinterpret_cast<PrimPair *>(rowmem);
     double *rows = rowmem + (size_t)a.npb * (sizeof(PrimPair) / sizeof(double));
+    // staged D rows of the bra (a.dstage): [nset][NI + NJ][ncols], column c
+    // holding the AO of the K row's column c
+    // (compiled in for the small bras only, where it can fit the LDS budget)
+    constexpr bool DST = k1_dstage_class(LI, LJ);
+    const bool dstage = DST && a.dstage;
+    const int dper = (NI + NJ) * ncols;
+    double *drows = rows + (size_t)per_set * a.nset;
+    const int n = a.nao;
     for (int t = tid; t < a.npb; t += NT) sbra[t] = a.pp[B.pp_off + t * B.pp_stride];
     for (int t = tid; t < per_set * a.nset; t += NT) rows[t] = 0.0;
+    if (dstage) {
+        for (int t = tid; t < dper * a.nset; t += NT) {
+            const int s = t / dper, e = t - s * dper;
+            const int r = e / ncols, c = e - r * ncols;
+            const int row = r < NI ? B.aoi + r : B.aoj + (r - NI);
+            const int col = c < a.ncolK ? a.aoc[a.tshK[c / NK]] + c % NK
+                                        : a.aoc[a.tshL[(c - a.ncolK) / NL]] + (c - a.ncolK) % NL;
+            drows[t] = a.D[s * a.mstride + (int64_t)row * n + col];
+        }
+    }
     __syncthreads();
-    const int n = a.nao;
     int evaluated = 0;  // quartets this wave evaluated (wave-uniform)
     for (int j0 = jbeg; j0 < cnt; j0 += NT) {
         if (!prefix_selectable(a, B.q, a.pairs[a.ket_list[j0]].q)) break;  // uniform in the workgroup
@@ -1028,19 +1045,37 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
             }
             if (a.do_k && valid) {
                 double djl[NJ * NL], djk[NJ * NK], dil[NI * NL], dik[NI * NK];
+                if (dstage) {
+                    const double *dr = drows + s * dper;
 #pragma unroll
-                for (int j2 = 0; j2 < NJ; ++j2) {
+                    for (int j2 = 0; j2 < NJ; ++j2) {
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) djl[j2 * NL + l] = D[(B.aoj + j2) * n + Kt.aoj + l];
+                        for (int l = 0; l < NL; ++l) djl[j2 * NL + l] = dr[(NI + j2) * ncols + cL + l];
 #pragma unroll
-                    for (int k = 0; k < NK; ++k) djk[j2 * NK + k] = D[(B.aoj + j2) * n + Kt.aoi + k];
-                }
+                        for (int k = 0; k < NK; ++k) djk[j2 * NK + k] = dr[(NI + j2) * ncols + cK + k];
+                    }
 #pragma unroll
-                for (int i2 = 0; i2 < NI; ++i2) {
+                    for (int i2 = 0; i2 < NI; ++i2) {
 #pragma unroll
-                    for (int l = 0; l < NL; ++l) dil[i2 * NL + l] = D[(B.aoi + i2) * n + Kt.aoj + l];
+                        for (int l = 0; l < NL; ++l) dil[i2 * NL + l] = dr[i2 * ncols + cL + l];
 #pragma unroll
-                    for (int k = 0; k < NK; ++k) dik[i2 * NK + k] = D[(B.aoi + i2) * n + Kt.aoi + k];
+                        for (int k = 0; k < NK; ++k) dik[i2 * NK + k] = dr[i2 * ncols + cK + k];
+                    }
+                } else {
+#pragma unroll
+                    for (int j2 = 0; j2 < NJ; ++j2) {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) djl[j2 * NL + l] = D[(B.aoj + j2) * n + Kt.aoj + l];
+#pragma unroll
+                        for (int k = 0; k < NK; ++k) djk[j2 * NK + k] = D[(B.aoj + j2) * n + Kt.aoi + k];
+                    }
+#pragma unroll
+                    for (int i2 = 0; i2 < NI; ++i2) {
+#pragma unroll
+                        for (int l = 0; l < NL; ++l) dil[i2 * NL + l] = D[(B.aoi + i2) * n + Kt.aoj + l];
+#pragma unroll
+                        for (int k = 0; k < NK; ++k) dik[i2 * NK + k] = D[(B.aoi + i2) * n + Kt.aoi + k];
+                    }
                 }
 #pragma unroll
                 for (int i2 = 0; i2 < NI; ++i2)

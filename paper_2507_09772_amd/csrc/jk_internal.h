@@ -181,6 +181,7 @@ struct jk_plan {
     int32_t *d_tpos = nullptr;                         // shell -> index within its type
     double dscreen = 0.0;  // density screening threshold for later builds (0: off)
     bool no_row = false;  // JK_NO_ROW=1 in the environment: tiles only (A/B measurements)
+    bool no_dstage = false;  // JK_NO_DSTAGE=1: family-1 rows read D from global memory (A/B measurements)
     double *d_dmax = nullptr;
     Tables tab{};
     jk_stats stats{};

@@ -35,6 +35,9 @@ inline size_t row_lds_bytes(const ClassEntry &e, int fam, int pr, int li, int lj
 // LDS budget of one row-mode workgroup (dynamic shared memory; gfx950 has
 // 160 KB per CU, kernels above 64 KB opt in through a function attribute).
 constexpr int ROW_LDS_MAX = 128 * 1024;
+// Family-1 long-bra rows stage the bra's D rows in LDS only while the
+// workgroup's LDS stays within this (so the staging does not cost occupancy).
+constexpr int DSTAGE_LDS_MAX = 40 * 1024;
 
 // Persistent form of the batched builds (kern_persist.hip): the family-1
 // 64-lane row tasks of the one- and two-root classes of every molecule in

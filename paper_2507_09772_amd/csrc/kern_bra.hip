@@ -32,7 +32,8 @@ static hipError_t lds_opt_in(K kernel, size_t lds, bool &done) {
 static size_t k1_row_lds(const JkArgs &a, int li, int lj) {
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
     return sizeof(PrimPair) * (size_t)a.npb +
-           sizeof(double) * a.nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj));
+           sizeof(double) * a.nset * ((size_t)(ncart(li) + ncart(lj)) * ncols + (size_t)ncart(li) * ncart(lj)) +
+           (a.dstage ? sizeof(double) * a.nset * (size_t)(ncart(li) + ncart(lj)) * ncols : 0);
 }
 
 template <int LI, int LJ, int LK, int LL, typename R, int NT>
