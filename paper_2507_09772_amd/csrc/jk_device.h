@@ -702,9 +702,13 @@ __device__ __forceinline__ void k1_compute_op(const JkArgs &a, const PairRec &B,
         // the root table row of the next primitive quartet is loaded while
         // the current one's recurrences run
         using P = RootPipe<NR, R>;
+        // the next ket primitive's record loads while the current one's bra
+        // primitives run
+        PrimPair pk = a.pp[Kt.pp_off];
+        settle(pk);
         for (int ik = 0; ik < npk; ++ik) {
-            PrimPair pk = a.pp[Kt.pp_off + ik * Kt.pp_stride];
-            settle(pk);
+            PrimPair pkn;
+            if (ik + 1 < npk) pkn = a.pp[Kt.pp_off + (ik + 1) * Kt.pp_stride];
             PT<R> t = prim_T<R>(pbat(0), pk);
             typename P::Row row;
             P::fetch(t.T, a.tab, row);
@@ -717,6 +721,10 @@ __device__ __forceinline__ void k1_compute_op(const JkArgs &a, const PairRec &B,
                     P::fetch(t.T, a.tab, row);
                 }
                 k1_roots_acc<LI, LJ, LK, LL, R>(g, u, w, ab, cd, V);
+            }
+            if (ik + 1 < npk) {
+                settle(pkn);
+                pk = pkn;
             }
         }
         return;
