@@ -286,6 +286,15 @@ int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precisio
  * 2048 for family 1, 256 wave steps for families 2 and 3); 0 restores a
  * default.  Table lines "shape li lj lk ll min_kets chunk". */
 int jk_tune_set_shape(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t min_kets, int32_t chunk);
+/* Mixed-precision split of one class, read by plans created afterwards
+ * (Section 4.3 leaves the split open; JK_MIXED applies it per quartet):
+ * 1 (the default) splits the class's quartets by their bound against the
+ * threshold; 0 runs the whole class in double precision in JK_MIXED builds,
+ * for classes whose single-precision kernels are no faster on the device
+ * (the split would only add a second pass; double precision is never less
+ * accurate).  Table lines "split li lj lk ll s".  JK_EINVAL for a class
+ * that is not canonical or built, or s not 0 or 1. */
+int jk_tune_set_split(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t split);
 int jk_tune_load(const char *path);
 
 const char *jk_last_error(void);

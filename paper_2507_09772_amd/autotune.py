@@ -1,6 +1,6 @@
 """Autotuner for the per-device kernel tuning table (tune_gfx950.txt).
 
-Two searches, each timing every class kernel through the library's
+Three searches, each timing every class kernel through the library's
 per-kernel timing (HIP events around each launch) on the given workloads:
 
 1. family and row mode: for each precision, every class forced to each
@@ -8,13 +8,19 @@ per-kernel timing (HIP events around each launch) on the given workloads:
    bra; per angular class the fastest (family, row) pair is kept;
 2. task shape (the fragmentation of Section 3.2): with those choices, the
    long-bra threshold (min_kets) and the kets per row task (chunk) from a
-   small grid around the defaults; per class the fastest pair is kept.
+   small grid around the defaults; per class the fastest pair is kept;
+3. mixed split: with those choices, each class's time in mixed builds
+   (its single- and double-precision passes) against its FP64 time; a
+   class whose mixed time is not at least 3 % lower runs in double
+   precision in mixed builds ("split li lj lk ll 0").
 
 Each class's time is summed over its primitive-count variants, the
 workloads and both kinds of launch (row tasks and tiles).  The table is
 written next to the library, which loads it at start-up.
 
 Run on the GPU: python -m paper_2507_09772_amd.autotune [--workloads c1 c2]
+(--split-only: keep the shipped table's families and shapes and redo the
+third search only).
 """
 from __future__ import annotations
 
@@ -39,6 +45,25 @@ def default_chunk(fam, li):
         return 2048
     nci = (li + 1) * (li + 2) // 2
     return 256 * max(1, 64 // nci)  # families 2 and 3 step by their quartets per wave
+
+
+def split_lines(jk, synth, torch, names):
+    """The third search: classes whose mixed builds are not faster."""
+    for c in jk.canonical_classes():
+        jk.tune_set_split(*c, 1)
+    t64 = timed_classes(jk, synth, torch, names, "fp64")
+    tmx = timed_classes(jk, synth, torch, names, "mixed")
+    lines, report = [], {}
+    for c in jk.canonical_classes():
+        if c not in t64 or c not in tmx:
+            continue
+        report[f"split ({c[0]}{c[1]}|{c[2]}{c[3]})"] = {"fp64": t64[c], "mixed": tmx[c]}
+        off = tmx[c] > 0.97 * t64[c]
+        print(f"split ({c[0]}{c[1]}|{c[2]}{c[3]}): fp64 {t64[c]:8.3f} mixed {tmx[c]:8.3f} ms -> "
+              f"{'off' if off else 'on'}", flush=True)
+        if off:
+            lines.append(f"split {c[0]} {c[1]} {c[2]} {c[3]} 0")
+    return lines, report
 
 
 def timed_classes(jk, synth, torch, names, precision, steps=2):
@@ -72,14 +97,26 @@ def main():
     ap.add_argument("--workloads", nargs="+", default=["c1", "c2"])
     ap.add_argument("--out", default=OUT)
     ap.add_argument("--no-shapes", action="store_true")
+    ap.add_argument("--split-only", action="store_true")
     args = ap.parse_args()
     import torch
 
     from paper_2507_09772_amd import jk, synth
+    if args.split_only:
+        keep = [l.rstrip("\n") for l in open(OUT) if not l.startswith("split")]
+        if not any(l.startswith("# split lines") for l in keep):
+            keep.insert(next(i for i, l in enumerate(keep) if not l.startswith("#")),
+                        "# split lines: li lj lk ll 0 (the class runs in double precision in mixed builds)")
+        lines, report = split_lines(jk, synth, torch, args.workloads)
+        with open(args.out, "w") as f:
+            f.write("\n".join(keep + lines) + "\n")
+        print(json.dumps(report), flush=True)
+        return
     lines = ["# kernel family per (class, precision), chosen by paper_2507_09772_amd/autotune.py",
              f"# workloads: {' '.join(args.workloads)}; columns: li lj lk ll precision(0 fp64, 2 fp32) family "
              "row(1 long bras, 2 off, 3 all bras)",
-             "# shape lines: li lj lk ll min_kets chunk (the long-bra threshold and kets per row task)"]
+             "# shape lines: li lj lk ll min_kets chunk (the long-bra threshold and kets per row task)",
+             "# split lines: li lj lk ll 0 (the class runs in double precision in mixed builds)"]
     report = {}
     choice = {}
     for precision in ("fp64", "fp32"):
@@ -125,8 +162,12 @@ def main():
             if (mk, sc) != (192, 1.0) and best < 0.97 * base:
                 lines.append(f"shape {c[0]} {c[1]} {c[2]} {c[3]} {mk} {int(default_chunk(fam, c[0]) * sc)}")
             report[f"shape ({c[0]}{c[1]}|{c[2]}{c[3]})"] = {f"m{k[0]}x{k[1]}": v for k, v in opts.items()}
+    split, rs = split_lines(jk, synth, torch, args.workloads)
+    lines += split
+    report.update(rs)
     for c in jk.canonical_classes():
         jk.tune_set_shape(*c, 0, 0)
+        jk.tune_set_split(*c, 1)
         for precision in ("fp64", "fp32"):
             jk.tune_set(*c, precision, 0)
             jk.tune_set_row(*c, precision, 0)

@@ -45,6 +45,9 @@ static int launch_counts(const jk_plan *P, std::vector<int64_t> *out);
 static const int ROW_MIN_KETS = 192;
 static int32_t g_minkets[NCLS];
 static int32_t g_chunk[NCLS];
+// Mixed-precision split per class: 0 default (split), 1 split, 2 the whole
+// class in double precision in mixed builds.
+static int32_t g_split[NCLS];
 
 // ---------------------------------------------------------------------------
 // errors
@@ -491,6 +494,7 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
                 if (!avail[f - 1]) f = 3 - f;
                 c.fam[pr] = f;
                 c.row_ok[pr] = g_row[class_id(c.li, c.lj, c.lk, c.ll)][pr] != 2;
+                c.split = g_split[class_id(c.li, c.lj, c.lk, c.ll)] != 2;
                 c.row_short[pr] = g_row[class_id(c.li, c.lj, c.lk, c.ll)][pr] == 3;
             }
             std::vector<int32_t> bl, cn, to[2];
@@ -709,6 +713,18 @@ extern "C" int jk_tune_set_shape(int32_t li, int32_t lj, int32_t lk, int32_t ll,
     return tune_set_shape_impl(li, lj, lk, ll, min_kets, chunk);
 }
 
+static int tune_set_split_impl(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t split) {
+    if (!valid_class(li, lj, lk, ll)) return fail(JK_EINVAL, "(%d%d|%d%d) is not a canonical built class", li, lj, lk, ll);
+    if (split != 0 && split != 1) return fail(JK_EINVAL, "split must be 0 or 1");
+    g_split[class_id(li, lj, lk, ll)] = split ? 1 : 2;
+    return 0;
+}
+
+extern "C" int jk_tune_set_split(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t split) {
+    ensure_tuning();
+    return tune_set_split_impl(li, lj, lk, ll, split);
+}
+
 extern "C" int jk_tune_get(int32_t li, int32_t lj, int32_t lk, int32_t ll, int32_t precision, int32_t *family,
                            int32_t *available) {
     ensure_tuning();
@@ -731,6 +747,17 @@ static int tune_load_impl(const char *path) {
         ++lineno;
         if (line[0] == '#' || line[0] == '\n') continue;
         int li, lj, lk, ll, pr, fam, row = 0;
+        if (strncmp(line, "split", 5) == 0) {
+            int sp = 1;
+            if (sscanf(line + 5, "%d %d %d %d %d", &li, &lj, &lk, &ll, &sp) != 5) {
+                fclose(f);
+                return fail(JK_EINVAL, "%s:%d: expected 'split li lj lk ll s'", path, lineno);
+            }
+            const int rc = tune_set_split_impl(li, lj, lk, ll, sp);
+            if (rc) { fclose(f); return rc; }
+            ++n;
+            continue;
+        }
         if (strncmp(line, "shape", 5) == 0) {
             int mk = 0, ch = 0;
             if (sscanf(line + 5, "%d %d %d %d %d %d", &li, &lj, &lk, &ll, &mk, &ch) != 6) {
@@ -984,10 +1011,11 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
         // mixed: a single-precision pass over the quartets below the
         // threshold, then a double-precision pass over the rest; both walk
         // the class's tiles and row tasks
-        const int npass = precision == JK_MIXED ? 2 : 1;
+        const bool msplit = precision == JK_MIXED && c.split;  // (else the class runs in FP64)
+        const int npass = msplit ? 2 : 1;
         for (int pass = 0; pass < npass; ++pass) {
-            const int pr = precision == JK_MIXED ? (pass == 0 ? 1 : 0) : (precision == JK_FP32 ? 1 : 0);
-            a.sel = precision == JK_MIXED ? (pass == 0 ? SEL_LO : SEL_HI) : SEL_ALL;
+            const int pr = msplit ? (pass == 0 ? 1 : 0) : (precision == JK_FP32 ? 1 : 0);
+            a.sel = msplit ? (pass == 0 ? SEL_LO : SEL_HI) : SEL_ALL;
             a.dstage = 0;
             const int f = c.fam[pr];
             // tiles (the short rest) of family 3 classes run in the fallback family

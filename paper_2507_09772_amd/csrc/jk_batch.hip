@@ -299,10 +299,11 @@ extern "C" int jk_batch_create(jk_plan *const *plans, int32_t nmol, int32_t nset
         md.sph = P->sph;
         for (size_t ci = 0; ci < P->cls.size(); ++ci) {
             const ClassTask &c = P->cls[ci];
-            const int npass = precision == JK_MIXED ? 2 : 1;
+            const bool msplit = precision == JK_MIXED && c.split;  // (else the class runs in FP64)
+            const int npass = msplit ? 2 : 1;
             for (int pass = 0; pass < npass; ++pass) {
-                const int pr = precision == JK_MIXED ? (pass == 0 ? 1 : 0) : (precision == JK_FP32 ? 1 : 0);
-                const int sel = precision == JK_MIXED ? (pass == 0 ? SEL_LO : SEL_HI) : SEL_ALL;
+                const int pr = msplit ? (pass == 0 ? 1 : 0) : (precision == JK_FP32 ? 1 : 0);
+                const int sel = msplit ? (pass == 0 ? SEL_LO : SEL_HI) : SEL_ALL;
                 int f = c.fam[pr];
                 const ClassEntry &ce = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
                 const int ncols = c.ncolK + (c.seg_same ? 0 : c.ncolL);

@@ -146,6 +146,7 @@ struct ClassTask {
     int ncolK = 0, ncolL = 0, seg_same = 0;
     const int32_t *d_tshK = nullptr, *d_tshL = nullptr;
     int fam[2];          // family per precision (0 FP64, 1 FP32)
+    bool split = true;   // mixed builds split this class by the bound (else all FP64)
     bool row_ok[2];      // row mode allowed per precision
     bool row_short[2];   // short bras in row mode too (64-lane workgroups)
     int ntiles[2];       // per family - 1

@@ -80,6 +80,7 @@ def lib():
         L.jk_tune_load.argtypes = [ctypes.c_char_p]
         L.jk_tune_set_row.argtypes = [i32, i32, i32, i32, i32, i32]
         L.jk_tune_set_shape.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.jk_tune_set_split.argtypes = [i32, i32, i32, i32, i32]
         L.jk_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -273,6 +274,13 @@ def tune_set_shape(li, lj, lk, ll, min_kets=0, chunk=0):
     """Task shape of one canonical class: long-bra threshold and kets per row
     task (0 = default)."""
     _check(lib().jk_tune_set_shape(li, lj, lk, ll, min_kets, chunk))
+
+
+def tune_set_split(li, lj, lk, ll, split=1):
+    """Mixed-precision split of one canonical class: 1 (default) splits its
+    quartets by the bound, 0 runs the class in double precision in mixed
+    builds."""
+    _check(lib().jk_tune_set_split(li, lj, lk, ll, split))
 
 
 def tune_get(li, lj, lk, ll, precision):

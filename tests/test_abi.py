@@ -92,7 +92,7 @@ def test_shipped_tuning_table_is_applied(jkmod):
     table is read after the kernel classes have registered)."""
     path = os.path.join(ROOT, "paper_2507_09772_amd", "tune_gfx950.txt")
     rows = [list(map(int, l.split())) for l in open(path)
-            if l.strip() and not l.startswith("#") and not l.startswith("shape")]
+            if l.strip() and not l.startswith("#") and not l.startswith(("shape", "split"))]
     assert rows
     for r in rows:
         li, lj, lk, ll, pr, fam = r[:6]
@@ -103,9 +103,18 @@ def test_shipped_tuning_table_is_applied(jkmod):
     for sh in shapes:
         assert len(sh) == 6
         jkmod.tune_set_shape(*map(int, sh))
+    # the mixed-split lines likewise
+    for sp in [l.split()[1:] for l in open(path) if l.startswith("split")]:
+        assert len(sp) == 5 and sp[4] in ("0", "1")
+        jkmod.tune_set_split(*map(int, sp))
+    jkmod.tune_load(path)
 
 
 def test_tuning_validation(jkmod):
+    with pytest.raises(jkmod.JKError):
+        jkmod.tune_set_split(0, 1, 0, 0, 0)   # not canonical
+    with pytest.raises(jkmod.JKError):
+        jkmod.tune_set_split(0, 0, 0, 0, 2)   # split is 0 or 1
     with pytest.raises(jkmod.JKError):
         jkmod.tune_set(0, 1, 0, 0, "fp64", 1)   # not canonical
     with pytest.raises(jkmod.JKError):

@@ -237,8 +237,19 @@ def test_density_screening(jkmod, torch_cuda, basis, nw, thr):
 # ---------------------------------------------------------------------------
 # mixed precision
 # ---------------------------------------------------------------------------
+@pytest.fixture
+def split_every_class(jkmod):
+    """The mixed split on in every class (the shipped table turns it off for
+    classes whose FP32 kernels are no faster), restored afterwards."""
+    import os
+    for c in jkmod.canonical_classes():
+        jkmod.tune_set_split(*c, 1)
+    yield
+    jkmod.tune_load(os.path.join(os.path.dirname(jkmod.__file__), "tune_gfx950.txt"))
+
+
 @pytest.mark.parametrize("basis,nw", [("A", 4), ("B", 4), ("A", 8), ("C", 2)])
-def test_mixed_small(jkmod, torch_cuda, basis, nw):
+def test_mixed_small(jkmod, torch_cuda, split_every_class, basis, nw):
     wl = synth.small_workload(nw, basis, seed=77)
     say("mixed", basis)
     J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
@@ -261,8 +272,44 @@ def test_mixed_small(jkmod, torch_cuda, basis, nw):
     assert plan.stats().nquartets_fp32 == plan.stats().nquartets
 
 
+def test_mixed_split_per_class(jkmod, torch_cuda):
+    """Classes with the mixed split off run in double precision in mixed
+    builds: with every class off the result is the FP64 build's (atomic
+    order aside) and no quartet is counted in FP32; with the higher classes
+    off the energies still meet the mixed bar against the oracle and fewer
+    quartets run in FP32."""
+    import os
+    wl = synth.small_workload(4, "B", seed=190)
+    say("mixed split per class")
+    J0, K0, _ = o.jk(wl.mol, wl.D, wl.cutoff, mode=1)
+    ej0, ek0 = o.energies(wl.D, J0, K0)
+    path = os.path.join(os.path.dirname(jkmod.__file__), "tune_gfx950.txt")
+    try:
+        for c in jkmod.canonical_classes():
+            jkmod.tune_set_split(*c, 1)
+        plan_on, _, _ = run_gpu(jkmod, torch_cuda, wl, precision="mixed")
+        n_on = plan_on.stats().nquartets_fp32
+        for c in jkmod.canonical_classes():
+            jkmod.tune_set_split(*c, 0)
+        plan, J64, K64 = run_gpu(jkmod, torch_cuda, wl)
+        _, J, K = run_gpu(jkmod, torch_cuda, wl, precision="mixed", plan=plan)
+        assert plan.stats().nquartets_fp32 == 0
+        assert np.abs(J - J64).max() <= 1e-13 and np.abs(K - K64).max() <= 1e-13
+        for c in jkmod.canonical_classes():
+            jkmod.tune_set_split(*c, 1 if sum(c) <= 2 else 0)
+        plan2, J, K = run_gpu(jkmod, torch_cuda, wl, precision="mixed")
+        n_part = plan2.stats().nquartets_fp32
+        assert 0 < n_part < n_on, (n_part, n_on)
+        ej, ek = o.energies(wl.D, J, K)
+        assert abs(ej[0] - ej0[0]) <= 1e-6 and abs(ek[0] - ek0[0]) <= 1e-6
+    finally:
+        for c in jkmod.canonical_classes():
+            jkmod.tune_set_split(*c, 1)
+        jkmod.tune_load(path)
+
+
 @pytest.mark.parametrize("basis,nw,thr", [("A", 5, 1e-3), ("B", 3, 1e-5), ("B", 4, 0.0), ("A", 3, 1e9)])
-def test_mixed_thresholds(jkmod, torch_cuda, basis, nw, thr):
+def test_mixed_thresholds(jkmod, torch_cuda, split_every_class, basis, nw, thr):
     """Threshold 0: nothing in FP32 (bit-identical to the FP64 build up to
     atomic ordering); a huge threshold: everything in FP32; in between the
     FP32 count follows the oracle's classification."""
