@@ -241,7 +241,7 @@ typedef struct {
     int32_t npb, npk;           /* primitive pairs per bra / ket pair */
     int32_t precision;          /* JK_FP64 or JK_FP32 */
     int32_t launches;           /* launches summed into ms (one per build) */
-    int32_t family;             /* kernel family (1, 2) */
+    int32_t family;             /* kernel family (1, 2 or 3) */
     int32_t kind;               /* 0 tiles, 1 row mode (long bras, 256-lane workgroups), 3 row mode
                                    (short bras, 64-lane workgroups); 2 is not used */
     int64_t nquartets;          /* quartets evaluated, summed over the launches (after the mixed
