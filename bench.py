@@ -101,6 +101,28 @@ def hbm_traffic(workload: str, kernel: str):
     return fetch + write, f"rocprofv3 FETCH_SIZE+WRITE_SIZE per dispatch, {os.path.relpath(path, ROOT)}"
 
 
+def counter_flops(workload: str, kernel: str):
+    """Hardware FP64 FLOP rate of `kernel` and of the whole build from the
+    committed rocprofv3 FLOP-counter summary (64 x SQ_INSTS_VALU_FLOPS_FP64
+    per dispatch over the traced average duration), or None while the
+    summary is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"jk_{workload}_fp64_flop_counters.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel sources sha256[^:]*: ([0-9a-f]+)", text)
+    if not m or m.group(1) != source_sha256():
+        return None
+    whole = re.search(r"counter FP64 FLOP rate ([0-9.]+) TFLOP/s", text)
+    kern = None
+    for line in text.splitlines():
+        f = line.split(None, 5)
+        if len(f) == 6 and f"jk::{kernel}(" in f[5]:
+            kern = float(f[3])
+    return {"kernel_tflops": kern, "build_tflops": float(whole.group(1)) if whole else None,
+            "source": os.path.relpath(path, ROOT)}
+
+
 def golden(name):
     path = os.path.join(GOLDEN, f"{name}_jk.json")
     if not os.path.exists(path):
@@ -179,9 +201,17 @@ def roofline_of(workload, kern, steps):
     peak = PEAK_FP64_VECTOR if k["precision"] == "fp64" else PEAK_FP32_VECTOR
     achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12
     traffic, src = hbm_traffic(workload, name)
-    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": traffic, "traffic_source": src, "kernel": name, "avg_launch_ms": k["ms"] / k["launches"],
-            "launches_per_build": k["launches"] / steps, "model_flops_per_launch": k["flops"] / k["launches"]}
+    out = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+           "traffic": traffic, "traffic_source": src, "kernel": name, "avg_launch_ms": k["ms"] / k["launches"],
+           "launches_per_build": k["launches"] / steps, "model_flops_per_launch": k["flops"] / k["launches"]}
+    cf = counter_flops(workload, name) if k["precision"] == "fp64" else None
+    if cf:
+        # the same kernel's hardware FLOP rate (rocprofv3 counters), and the whole build's
+        out["counter_achieved"] = cf["kernel_tflops"]
+        out["counter_frac"] = cf["kernel_tflops"] / peak if cf["kernel_tflops"] else None
+        out["counter_build_tflops"] = cf["build_tflops"]
+        out["counter_source"] = cf["source"]
+    return out
 
 
 def errors_vs_golden(g, D, J, K):
