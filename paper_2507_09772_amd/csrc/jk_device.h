@@ -1223,7 +1223,11 @@ struct K2Cfg {
         return pb < 1 ? 1 : pb;
     }
     static constexpr int PB = pb_();
-    static constexpr int TAB = PB * RB * 3 * C::S;            // 2-D table entries per quartet
+    // one (primitive, root, direction) table is S entries, stored SP apart:
+    // an odd stride, so the table-building lanes of a wave (one table each)
+    // write to different LDS banks
+    static constexpr int SP = C::S % 2 == 0 ? C::S + 1 : C::S;
+    static constexpr int TAB = PB * RB * 3 * SP;              // 2-D table entries per quartet
     // LDS digestion blocks: jij, jkl, kik, kil, kjk, kjl
     static constexpr int O_JIJ = 0;
     static constexpr int O_JKL = O_JIJ + C::NI * C::NJ;
@@ -1256,7 +1260,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                                         int64_t gq, double *rows = nullptr, int ncols = 0, int segL = 0) {
     using C = Cls<LI, LJ, LK, LL>;
     using F = K2Cfg<LI, LJ, LK, LL>;
-    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, S = C::S;
+    constexpr int NI = C::NI, NJ = C::NJ, NK = C::NK, NL = C::NL, NR = C::NR, S = F::SP;
     constexpr int QW = F::QW, LPQ = F::LPQ, SPL = F::SPL, CB = F::CB, NPASS = F::NPASS, PB = F::PB;
     const int lane = lane_index();
     const int q = QW > 1 ? lane / LPQ : 0;
