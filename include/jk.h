@@ -135,7 +135,11 @@ int jk_plan_schwarz(const jk_plan *plan, double *Q_host);
  * stream (unless JK_CHECK_SYMMETRY); D/J/K must stay valid until the stream
  * reaches this point.  nset >= 1.  Scratch (Cartesian J', K', density, the
  * block maxima) is allocated by the plan at the first call that needs it
- * and reused; calls on one plan must be ordered.
+ * and reused; calls on one plan must be ordered.  The class kernels run on
+ * stream and on up to three more streams of the plan (JK_STREAMS=n in the
+ * environment at plan creation sets the total, 1 to 8, default 4), forked
+ * from stream by an event and joined back into it before J and K are
+ * written, so the build stays ordered on stream (also under graph capture).
  */
 int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int32_t precision,
                double mix_threshold, double omega, double *J, double *K, void *stream);
@@ -230,8 +234,8 @@ int jk_boys_eval(int32_t m, const double *T_host, int32_t count, int32_t precisi
 
 /*
  * Per-kernel timing (measurement support).  While enabled, jk_execute
- * records a HIP event on its stream before and after every class-kernel
- * launch, waits for the last one before returning, and adds each launch's
+ * launches every class kernel on its stream, one after another, records a
+ * HIP event on that stream before and after every class-kernel launch, waits for the last one before returning, and adds each launch's
  * duration to the running total of its (class, precision, kind) entry.
  * jk_plan_profile(plan, 1) resets the totals; jk_plan_timings copies up to
  * cap entries (those that ran) and stores the number available in *count.

@@ -298,6 +298,16 @@ extern "C" int jk_plan_create(const jk_basis *basis, double cutoff, jk_plan **ou
     HIPCHK(hipGetDevice(&P->device));
     if ((rc = tables_for_device(&P->tab))) return rc;
     {
+        const char *ns = getenv("JK_STREAMS");
+        const int nsv = ns && *ns ? atoi(ns) : 4;
+        P->nstream = std::max(1, std::min(nsv, (int)jk_plan::MAXSTREAM));
+    }
+    HIPCHK(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+    for (int k = 1; k < P->nstream; ++k) {
+        HIPCHK(hipStreamCreateWithFlags(&P->streams[k], hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&P->join_ev[k], hipEventDisableTiming));
+    }
+    {
         const char *nr = getenv("JK_NO_ROW");
         P->no_row = nr && nr[0] == '1';
         const char *nd = getenv("JK_NO_DSTAGE");
@@ -1000,9 +1010,27 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
         if (slot >= 0) slots.push_back(slot);
         return 0;
     };
+    // the class launches only add into Jc, Kc and jp with atomics, so
+    // classes may overlap: each class goes whole to the least loaded of the
+    // plan's streams (by model flops), forked from s and joined back into s
+    // before the J'_KL scatter. Timed builds stay on s.
+    const hipStream_t s0 = s;
+    const int nst = profile ? 1 : P->nstream;
+    double load[jk_plan::MAXSTREAM] = {};
+    if (nst > 1) {
+        HIPCHK(hipEventRecord(P->fork_ev, s0));
+        for (int k = 1; k < nst; ++k) HIPCHK(hipStreamWaitEvent(P->streams[k], P->fork_ev, 0));
+    }
     for (size_t ci = 0; ci < P->cls.size(); ++ci) {
         const ClassTask &c = P->cls[ci];
         const ClassEntry &e = g_classes[class_id(c.li, c.lj, c.lk, c.ll)];
+        if (nst > 1) {
+            int k = 0;
+            for (int t = 1; t < nst; ++t)
+                if (load[t] < load[k]) k = t;
+            load[k] += c.flops;
+            s = k == 0 ? s0 : P->streams[k];
+        }
         a.ket_list = c.d_ket;
         a.same = c.same;
         a.npb = c.npb;
@@ -1084,6 +1112,11 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
                 HIPCHK(e.tiles[ft - 1][pr](a, s));
             }
         }
+    }
+    s = s0;
+    for (int k = 1; k < nst; ++k) {
+        HIPCHK(hipEventRecord(P->join_ev[k], P->streams[k]));
+        HIPCHK(hipStreamWaitEvent(s0, P->join_ev[k], 0));
     }
     if (profile) {
         if ((rc = mark(-1))) return rc;

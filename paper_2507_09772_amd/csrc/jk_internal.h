@@ -187,6 +187,13 @@ struct jk_plan {
     Tables tab{};
     jk_stats stats{};
     int device = 0;
+    // class kernels of one build spread over the caller's stream and these
+    // (JK_STREAMS, default 4 in all; default priority, non-blocking), forked
+    // from and joined back into the caller's stream by events
+    static constexpr int MAXSTREAM = 8;
+    int nstream = 1;
+    hipStream_t streams[MAXSTREAM] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[MAXSTREAM] = {};
     // per-kernel timing
     bool profile = false;
     std::vector<hipEvent_t> events;
@@ -209,6 +216,11 @@ struct jk_plan {
     }
     ~jk_plan() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (int k = 1; k < nstream; ++k) {
+            if (streams[k]) (void)hipStreamDestroy(streams[k]);
+            if (join_ev[k]) (void)hipEventDestroy(join_ev[k]);
+        }
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
         for (void *p : allocs) (void)hipFree(p);
     }
 };
