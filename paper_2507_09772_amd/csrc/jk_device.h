@@ -1206,11 +1206,21 @@ struct K2Cfg {
     static constexpr int CB = cb_();
     static constexpr int NPASS = (C::NJ + CB - 1) / CB;
     // roots whose tables are held at once: all of them where the wave's
-    // tables fit 48 KB (in FP64), otherwise blocks of RB roots one after
-    // another (the high classes of g shells)
-    static constexpr int RB = (QW * C::NR * 3 * C::S * 8 <= 48 * 1024) ? C::NR
-                              : ((48 * 1024) / (QW * 3 * C::S * 8) > 0 ? (48 * 1024) / (QW * 3 * C::S * 8) : 1);
+    // tables fit 56 KB (in FP64), otherwise blocks of RB roots within 48 KB
+    // one after another.  Blocks cost a table build per block and b-chunk
+    // pass (the tables of one block do not outlive the pass), which the
+    // classes whose tables take 49-53 KB ((gf|ff), (gf|gd), (gg|fd)) lose
+    // more to than to the lower occupancy of the larger LDS block; above
+    // that the occupancy loss dominates.
+    static constexpr int TAB_ALL = 56 * 1024, TAB_BLK = 48 * 1024;
+    static constexpr int RB = (QW * C::NR * 3 * C::S * 8 <= TAB_ALL) ? C::NR
+                              : (TAB_BLK / (QW * 3 * C::S * 8) > 0 ? TAB_BLK / (QW * 3 * C::S * 8) : 1);
     static constexpr int NRB = (C::NR + RB - 1) / RB;
+    // roots of a block unrolled in the accumulation: all of them while a
+    // root's products are few; above that the unrolled block keeps more
+    // table values in flight than the register file holds (the kernels
+    // spilled up to 2.5 KB per lane), so the roots then run as a loop
+    static constexpr int RUNROLL = SPL * CB * C::NL * RB > 96 ? 1 : RB;
     // primitive quartets whose tables are built at once: enough that every
     // lane of a quartet's group has a (primitive, root, direction) task,
     // within 24 KB of tables per wave (in FP64); one where the roots come in
@@ -1363,7 +1373,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
             }
             for (int p = 0; p < PB; ++p) {
             if (it0 + p >= nit) break;  // uniform in the wave
-#pragma unroll
+#pragma unroll F::RUNROLL
             for (int rl = 0; rl < RB; ++rl) {
                 if (r0 + rl >= NR) continue;
                 const R *tr = tq + (p * RB + rl) * 3 * S;
