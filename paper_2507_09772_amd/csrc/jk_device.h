@@ -1862,10 +1862,10 @@ __global__ void __launch_bounds__(NT) jk_k3_row(const JkArgs a_in, const BatchDe
                 const R *gp = gq + p * NR * 3 * F::GS;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) {
-                    R T[3][TS];
-#pragma unroll
-                    for (int x = 0; x < 3; ++x)
-                        hrr_lane<LJ, LK, LL, R>(gp + (r * 3 + x) * F::GS + ae[x] * (NCC + 1), ab[x], cd[x], T[x]);
+                    R T0[TS], T1[TS], T2[TS];
+                    hrr_lane<LJ, LK, LL, R>(gp + (r * 3 + 0) * F::GS + ae[0] * (NCC + 1), ab[0], cd[0], T0);
+                    hrr_lane<LJ, LK, LL, R>(gp + (r * 3 + 1) * F::GS + ae[1] * (NCC + 1), ab[1], cd[1], T1);
+                    hrr_lane<LJ, LK, LL, R>(gp + (r * 3 + 2) * F::GS + ae[2] * (NCC + 1), ab[2], cd[2], T2);
 #pragma unroll
                     for (int b = 0; b < NJ; ++b)
 #pragma unroll
@@ -1875,7 +1875,7 @@ __global__ void __launch_bounds__(NT) jk_k3_row(const JkArgs a_in, const BatchDe
                                 const int ix = (cart_comp(LJ, b, 0) * (LK + 1) + cart_comp(LK, c, 0)) * (LL + 1) + cart_comp(LL, d, 0);
                                 const int iy = (cart_comp(LJ, b, 1) * (LK + 1) + cart_comp(LK, c, 1)) * (LL + 1) + cart_comp(LL, d, 1);
                                 const int iz = (cart_comp(LJ, b, 2) * (LK + 1) + cart_comp(LK, c, 2)) * (LL + 1) + cart_comp(LL, d, 2);
-                                V[(b * NK + c) * NL + d] += T[0][ix] * T[1][iy] * T[2][iz];
+                                V[(b * NK + c) * NL + d] += T0[ix] * T1[iy] * T2[iz];
                             }
                 }
             }
