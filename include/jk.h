@@ -62,9 +62,21 @@ enum {
     JK_DO_J = 1,
     JK_DO_K = 2,
     JK_ACCUMULATE = 4,     /* add into J/K instead of overwriting them */
-    JK_CHECK_SYMMETRY = 8  /* check on the device that every D is finite and
+    JK_CHECK_SYMMETRY = 8, /* check on the device that every D is finite and
                               symmetric (max|D - D^T| <= 1e-12 max|D|) before the
                               build; JK_EINVAL otherwise.  Synchronises the stream */
+    JK_DETERMINISTIC = 16  /* bitwise the same J and K on every run, every stream
+                              count and every launch order: each addition into
+                              J', K' and the pair-ordered J' is split exactly into
+                              three 64-bit integer limbs (2^-16, 2^-56 and a
+                              rounded 2^-96 part) added with integer atomics, and
+                              the limbs are summed in a fixed order at the end.
+                              Every class runs as tiles (no row mode).  Needs
+                              |addend| < 2^24 and at most 2^23 additions per
+                              element; takes 9 x max(nset nao_cart^2, nset x the
+                              pair-block elements) more doubles of plan scratch
+                              and is slower than the default.  jk_execute only
+                              (jk_execute_noalloc returns JK_EINVAL) */
 };
 
 #define JK_LMAX 4       /* highest angular momentum the basis format admits (g) */
@@ -159,7 +171,8 @@ int jk_execute(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int3
  * calls that overlap on one GPU race (order them on one stream), and
  * jk_plan_stats after such a call reads the counters the last call on that
  * GPU wrote.  Each call clears what it accumulates into.  Per-kernel
- * profiling (jk_plan_profile) does not apply to it.
+ * profiling (jk_plan_profile) does not apply to it, and JK_DETERMINISTIC
+ * (whose limbs the array does not hold) returns JK_EINVAL.
  */
 #define JK_NOALLOC_SCRATCH_BYTES (128u << 20)
 int jk_execute_noalloc(jk_plan *plan, const double *D, int32_t nset, int32_t flags, int32_t precision,

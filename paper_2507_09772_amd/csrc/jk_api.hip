@@ -155,6 +155,17 @@ __global__ void k_fill_i32(int32_t *p, int n) {
     for (int t = threadIdx.x; t < n; t += blockDim.x) p[t] = 0;
 }
 
+// The fixed-order limbs of elements 0..n-1 (limbs L apart) into doubles, in
+// place over the first limb: the smallest part first, the same order for
+// every element and every build.
+__global__ void k_det_collapse(double *p, int64_t L, int64_t n) {
+    const long long *q = reinterpret_cast<const long long *>(p);
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const long long q0 = q[t], q1 = q[t + L], q2 = q[t + 2 * L];
+        p[t] = ((double)q2 * 0x1p-96 + (double)q1 * 0x1p-56) + (double)q0 * 0x1p-16;
+    }
+}
+
 __global__ void k_jp_scatter(const PairRec *pairs, const int32_t *lsh, const double *jp, int64_t jpstride, double *Jc,
                              int64_t mstride, int naoc, int npair, int64_t nt) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
@@ -841,9 +852,19 @@ static void drop_alloc(jk_plan *P, void *p) {
 }
 
 // The plan's own scratch, grown on demand (jk_execute).
-static int ensure_scratch(jk_plan *P, int nset, Scratch *sc) {
+static int ensure_scratch(jk_plan *P, int nset, Scratch *sc, bool det = false) {
     const size_t m = (size_t)P->naoc * P->naoc;
     int rc;
+    // the fixed-order limbs: one length for the three buffers, so that a
+    // kernel finds every limb at the same distance
+    const int64_t L = (int64_t)std::max(m * nset, (size_t)P->njp * nset);
+    if (det && P->det_len < L) {
+        drop_alloc(P, P->d_det);
+        P->d_det = nullptr;
+        P->det_len = 0;
+        if ((rc = P->alloc(&P->d_det, 9 * (size_t)L))) return rc;
+        P->det_len = L;
+    }
     if (P->scratch_nset < nset) {
         drop_alloc(P, P->d_Jc);
         drop_alloc(P, P->d_Kc);
@@ -865,6 +886,10 @@ static int ensure_scratch(jk_plan *P, int nset, Scratch *sc) {
     if (!P->d_dmax && (rc = P->alloc(&P->d_dmax, scratch_sizes(P, 1).dmax))) return rc;
     if (!P->d_nsel && (rc = P->alloc(&P->d_nsel, scratch_sizes(P, 1).nsel))) return rc;
     *sc = Scratch{P->d_Jc, P->d_Kc, P->d_Dc, P->d_jp, P->d_dmax, P->d_nsel};
+    if (det) {
+        sc->det = P->d_det;
+        sc->detL = L;
+    }
     return 0;
 }
 
@@ -896,7 +921,8 @@ int check_execute_args(const jk_plan *P, const double *D, int32_t nset, int32_t 
     if (!P) return fail(JK_EINVAL, "plan is NULL");
     if (!D || nset < 1) return fail(JK_EINVAL, "D must be non-NULL and nset >= 1");
     const bool do_j = flags & JK_DO_J, do_k = flags & JK_DO_K;
-    if (flags & ~(JK_DO_J | JK_DO_K | JK_ACCUMULATE | JK_CHECK_SYMMETRY)) return fail(JK_EINVAL, "unknown flag bits 0x%x", flags);
+    if (flags & ~(JK_DO_J | JK_DO_K | JK_ACCUMULATE | JK_CHECK_SYMMETRY | JK_DETERMINISTIC))
+        return fail(JK_EINVAL, "unknown flag bits 0x%x", flags);
     if ((do_j && !J) || (do_k && !K)) return fail(JK_EINVAL, "J/K output missing for a requested matrix");
     if (precision != JK_FP64 && precision != JK_MIXED && precision != JK_FP32) return fail(JK_EINVAL, "bad precision %d", precision);
     if (precision == JK_MIXED && !(std::isfinite(mix_threshold) && mix_threshold >= 0.0)) return fail(JK_EINVAL, "mix_threshold must be finite and >= 0");
@@ -944,18 +970,29 @@ static int check_symmetry(const jk_plan *P, const double *D, int nset, hipStream
 int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32_t precision, double mix_threshold,
                         double omega, double *J, double *K, hipStream_t s, const Scratch &sc, bool allow_profile) {
     const bool do_j = flags & JK_DO_J, do_k = flags & JK_DO_K;
+    const bool det = flags & JK_DETERMINISTIC;
     int rc;
+    if (det && !sc.det) return fail(JK_EINVAL, "JK_DETERMINISTIC needs the plan's own scratch (jk_execute)");
     if ((flags & JK_CHECK_SYMMETRY) && (rc = check_symmetry(P, D, nset, s, sc.nsel))) return rc;
     const size_t m = (size_t)P->naoc * P->naoc;
+    // accumulation targets: FP64 buffers, or in the fixed-order mode the
+    // three limb buffers (J', K', pair-ordered J'), each 3 x detL elements
+    double *const Jc = det ? sc.det : sc.Jc;
+    double *const Kc = det ? sc.det + 3 * sc.detL : sc.Kc;
+    double *const jpb = det ? sc.det + 6 * sc.detL : sc.jp;
     const double *Dc = D;
     if (P->sph) {
         hipLaunchKernelGGL(k_sph_to_cart, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, P->maps, D, sc.Dc, P->nao, P->naoc, nset);
         HIPCHK(hipGetLastError());
         Dc = sc.Dc;
     }
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, sc.Jc, (int64_t)(nset * m), 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, sc.Kc, (int64_t)(nset * m), 0.0);
-    hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * P->njp, 256)), dim3(256), 0, s, sc.jp, (int64_t)nset * P->njp, 0.0);
+    if (det) {
+        hipLaunchKernelGGL(k_fill, dim3(grid_for(9 * sc.detL, 256)), dim3(256), 0, s, sc.det, 9 * sc.detL, 0.0);
+    } else {
+        hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, Jc, (int64_t)(nset * m), 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * m, 256)), dim3(256), 0, s, Kc, (int64_t)(nset * m), 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(grid_for((int64_t)nset * P->njp, 256)), dim3(256), 0, s, jpb, (int64_t)nset * P->njp, 0.0);
+    }
     const int nctr = (int)scratch_sizes(P, nset).nsel;
     hipLaunchKernelGGL(k_fill_u64, dim3((nctr + 255) / 256), dim3(256), 0, s, sc.nsel, nctr);
     HIPCHK(hipGetLastError());
@@ -968,10 +1005,11 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
     a.pairs = P->d_pairs;
     a.pp = P->d_pp;
     a.D = Dc;
-    a.J = sc.Jc;
-    a.K = sc.Kc;
+    a.J = Jc;
+    a.K = Kc;
     a.mstride = (int64_t)m;
-    a.jp = sc.jp;
+    a.jp = jpb;
+    a.det = det ? sc.detL : 0;
     a.jpstride = P->njp;
     a.nao = P->naoc;
     a.nset = nset;
@@ -1054,7 +1092,9 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
             // quartets are the first few kets of each bra (largest Schwarz
             // factors), a fraction of one row-mode pass per bra, and tiles
             // past them end at their first ket
-            const bool tiles_only = a.sel == SEL_HI;
+            // (and every class in the fixed-order mode: the row kernels add
+            // into their LDS rows from several waves, in no fixed order)
+            const bool tiles_only = a.sel == SEL_HI || det;
             const bool longrows = !tiles_only && c.row_ok[pr] && c.nrow > 0 && e.row[f - 1][pr] &&
                                   row_lds_bytes(e, f, pr, c.li, c.lj, nset, ncols, 4, c.npb) <= (size_t)ROW_LDS_MAX && !P->no_row;
             const bool shortrows = !tiles_only && c.row_short[pr] && c.nsrow > 0 && e.srow[f - 1][pr] &&
@@ -1138,13 +1178,19 @@ int execute_impl(jk_plan *P, const double *D, int32_t nset, int32_t flags, int32
     const int acc = (flags & JK_ACCUMULATE) ? 1 : 0;
     const int64_t mo = (int64_t)nset * P->nao * P->nao;
     const int npair = (int)P->hpairs.size();
+    if (det) {
+        const int64_t nm = (int64_t)nset * m, nj = (int64_t)nset * P->njp;
+        hipLaunchKernelGGL(k_det_collapse, dim3(grid_for(nm, 256)), dim3(256), 0, s, Jc, sc.detL, nm);
+        hipLaunchKernelGGL(k_det_collapse, dim3(grid_for(nm, 256)), dim3(256), 0, s, Kc, sc.detL, nm);
+        hipLaunchKernelGGL(k_det_collapse, dim3(grid_for(nj, 256)), dim3(256), 0, s, jpb, sc.detL, nj);
+    }
     if (do_j) {
         const int64_t nt = (int64_t)nset * npair * 64;
-        hipLaunchKernelGGL(k_jp_scatter, dim3(grid_for(nt, 256)), dim3(256), 0, s, P->d_pairs, P->maps.l, sc.jp, P->njp,
-                           sc.Jc, (int64_t)m, P->naoc, npair, nt);
+        hipLaunchKernelGGL(k_jp_scatter, dim3(grid_for(nt, 256)), dim3(256), 0, s, P->d_pairs, P->maps.l, jpb, P->njp,
+                           Jc, (int64_t)m, P->naoc, npair, nt);
     }
-    if (do_j) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, sc.Jc, J, P->nao, P->naoc, nset, P->sph, acc);
-    if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, sc.Kc, K, P->nao, P->naoc, nset, P->sph, acc);
+    if (do_j) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, Jc, J, P->nao, P->naoc, nset, P->sph, acc);
+    if (do_k) hipLaunchKernelGGL(k_finalize, dim3(grid_for(mo, 256)), dim3(256), 0, s, P->maps, Kc, K, P->nao, P->naoc, nset, P->sph, acc);
     HIPCHK(hipGetLastError());
     return JK_OK;
 }
@@ -1154,7 +1200,7 @@ extern "C" int jk_execute(jk_plan *P, const double *D, int32_t nset, int32_t fla
     int rc = check_execute_args(P, D, nset, flags, precision, mix_threshold, omega, J, K);
     if (rc) return rc;
     Scratch sc;
-    if ((rc = ensure_scratch(P, nset, &sc))) return rc;
+    if ((rc = ensure_scratch(P, nset, &sc, (flags & JK_DETERMINISTIC) != 0))) return rc;
     return execute_impl(P, D, nset, flags, precision, mix_threshold, omega, J, K, (hipStream_t)stream, sc, true);
 }
 

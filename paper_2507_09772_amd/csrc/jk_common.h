@@ -140,6 +140,10 @@ struct JkArgs {
     // columns are staged in LDS once per task (1), so the exchange digestion
     // reads them there instead of four scattered global loads per element
     int32_t dstage;
+    // fixed-order accumulation (JK_DETERMINISTIC): J, K and jp each hold
+    // three 64-bit integer limbs per element, det elements apart (0: FP64
+    // atomics)
+    int64_t det;
     // densities and results (Cartesian, [nset][nao][nao])
     const double *D;
     double *J, *K;

@@ -468,6 +468,32 @@ __device__ __forceinline__ void atomic_add_f64(double *p, T v) {
     unsafeAtomicAdd(p, (double)v);
 }
 
+// Fixed-order accumulation.  v is split exactly into integer multiples of
+// 2^-16 and 2^-56 and a multiple of 2^-96 rounded to nearest (each below
+// 2^40 in magnitude for |v| < 2^24), and each part is added to its own
+// 64-bit integer limb, L elements apart.  Integer additions commute, so the
+// limbs end the same whatever order the additions came in, for up to 2^23
+// additions per element; k_det_collapse then forms the double in a fixed
+// order.
+__device__ __forceinline__ void det_add(double *p, int64_t L, double v) {
+    if (v == 0.0) return;
+    unsigned long long *q = reinterpret_cast<unsigned long long *>(p);
+    const double x0 = v * 0x1p16;
+    const double t0 = trunc(x0);
+    const double x1 = (x0 - t0) * 0x1p40;
+    const double t1 = trunc(x1);
+    const double t2 = rint((x1 - t1) * 0x1p40);
+    if (t0 != 0.0) atomicAdd(q, (unsigned long long)(long long)t0);
+    if (t1 != 0.0) atomicAdd(q + L, (unsigned long long)(long long)t1);
+    if (t2 != 0.0) atomicAdd(q + 2 * L, (unsigned long long)(long long)t2);
+}
+// A tile kernel's addition into J, K or the pair-ordered J' buffer.
+template <typename T>
+__device__ __forceinline__ void acc_add(const JkArgs &a, double *p, T v) {
+    if (a.det) det_add(p, a.det, (double)v);
+    else atomic_add_f64(p, v);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -812,7 +838,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
 #pragma unroll
                     for (int m = 0; m < NM; ++m) {
                         const int e = lane + 64 * m;
-                        if (e < NAB) atomic_add_f64(&Jm[(B.aoi + e / NJ) * n + B.aoj + e % NJ], mine[m]);
+                        if (e < NAB) acc_add(a, &Jm[(B.aoi + e / NJ) * n + B.aoj + e % NJ], mine[m]);
                     }
                 } else if (valid) {
 #pragma unroll
@@ -820,7 +846,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                         double s2 = 0.0;
 #pragma unroll
                         for (int cd2 = 0; cd2 < NCD; ++cd2) s2 += (double)V[ab2 * NCD + cd2] * dkl[cd2];
-                        atomic_add_f64(&Jm[(B.aoi + ab2 / NJ) * n + B.aoj + ab2 % NJ], w2 * s2);
+                        acc_add(a, &Jm[(B.aoi + ab2 / NJ) * n + B.aoj + ab2 % NJ], w2 * s2);
                     }
                 }
                 if (valid) {
@@ -832,7 +858,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                         double s2 = 0.0;
 #pragma unroll
                         for (int ab2 = 0; ab2 < NAB; ++ab2) s2 += (double)V[ab2 * NCD + cd2] * dij[ab2];
-                        atomic_add_f64(&jq[(int64_t)cd2 * Kt.pp_stride], w2 * s2);
+                        acc_add(a, &jq[(int64_t)cd2 * Kt.pp_stride], w2 * s2);
                     }
                 }
             }
@@ -861,7 +887,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                         for (int j = 0; j < NJ; ++j)
 #pragma unroll
                             for (int l = 0; l < NL; ++l) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * djl[j * NL + l];
-                        atomic_add_f64(&Km[(B.aoi + i) * n + Kt.aoi + k], wq * s2);
+                        acc_add(a, &Km[(B.aoi + i) * n + Kt.aoi + k], wq * s2);
                     }
 #pragma unroll
                 for (int i = 0; i < NI; ++i)
@@ -872,7 +898,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                         for (int j = 0; j < NJ; ++j)
 #pragma unroll
                             for (int k = 0; k < NK; ++k) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * djk[j * NK + k];
-                        atomic_add_f64(&Km[(B.aoi + i) * n + Kt.aoj + l], wq * s2);
+                        acc_add(a, &Km[(B.aoi + i) * n + Kt.aoj + l], wq * s2);
                     }
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
@@ -883,7 +909,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                         for (int i = 0; i < NI; ++i)
 #pragma unroll
                             for (int l = 0; l < NL; ++l) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * dil[i * NL + l];
-                        atomic_add_f64(&Km[(B.aoj + j) * n + Kt.aoi + k], wq * s2);
+                        acc_add(a, &Km[(B.aoj + j) * n + Kt.aoi + k], wq * s2);
                     }
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
@@ -894,7 +920,7 @@ __device__ __forceinline__ void k1_body(const JkArgs &a, int bra, int ket, bool 
                         for (int i = 0; i < NI; ++i)
 #pragma unroll
                             for (int k = 0; k < NK; ++k) s2 += (double)V[((i * NJ + j) * NK + k) * NL + l] * dik[i * NK + k];
-                        atomic_add_f64(&Km[(B.aoj + j) * n + Kt.aoj + l], wq * s2);
+                        acc_add(a, &Km[(B.aoj + j) * n + Kt.aoj + l], wq * s2);
                     }
             }
         }
@@ -1514,7 +1540,7 @@ __device__ __forceinline__ void k2_body(const JkArgs &a, R *tabs, double *dig, i
                         else if (t < F::O_KJK) { const int e = t - F::O_KIL; row = B.aoi + e / NL; col = Kt.aoj + e % NL; M = Km; }
                         else if (t < F::O_KJL) { const int e = t - F::O_KJK; row = B.aoj + e / NK; col = Kt.aoi + e % NK; M = Km; }
                         else { const int e = t - F::O_KJL; row = B.aoj + e / NL; col = Kt.aoj + e % NL; M = Km; }
-                        atomic_add_f64(&M[row * n + col], v);
+                        acc_add(a, &M[row * n + col], v);
                     }
                 }
             }

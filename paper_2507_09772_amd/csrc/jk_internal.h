@@ -172,6 +172,8 @@ struct jk_plan {
     double *d_Jc = nullptr, *d_Kc = nullptr, *d_Dc = nullptr;
     int scratch_nset = 0, dc_nset = 0;
     double *d_jp = nullptr;  // pair-ordered J'_KL buffer [scratch_nset][njp]
+    double *d_det = nullptr;  // JK_DETERMINISTIC limbs, 9 x det_len elements
+    int64_t det_len = 0;
     int64_t njp = 0;
     // quartets evaluated per launch of the last build: [class][precision][kind]
     // counted on the device (NSEL_SLOTS counters each), or known on the host
@@ -230,6 +232,10 @@ struct jk_plan {
 struct Scratch {
     double *Jc, *Kc, *Dc, *jp, *dmax;
     unsigned long long *nsel;
+    // JK_DETERMINISTIC: J', K' and the pair-ordered J' as integer limbs,
+    // [3 buffers][3 limbs][detL] (null when the caller's scratch has none)
+    double *det = nullptr;
+    int64_t detL = 0;
 };
 
 // Elements of each scratch array for a build with nset densities.

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libjk.so")
 
 JK_OK, JK_EINVAL, JK_EUNSUPPORTED, JK_ENOMEM, JK_EDEVICE = 0, -1, -2, -3, -4
 JK_FP64, JK_MIXED, JK_FP32 = 0, 1, 2
-JK_DO_J, JK_DO_K, JK_ACCUMULATE, JK_CHECK_SYMMETRY = 1, 2, 4, 8
+JK_DO_J, JK_DO_K, JK_ACCUMULATE, JK_CHECK_SYMMETRY, JK_DETERMINISTIC = 1, 2, 4, 8, 16
 PRECISION = {"fp64": JK_FP64, "mixed": JK_MIXED, "fp32": JK_FP32}
 
 
