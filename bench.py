@@ -279,6 +279,9 @@ def bench_molecule(name, args, torch, jk, synth, steps, warmup):
         res[prec] = r
     if "fp64" in res and "mixed" in res:
         res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    if name in ("c1", "c2") and "fp64" in res:
+        res["deterministic"] = bench_deterministic(torch, jk, plan, D, g, wl, res["fp64"]["ms_per_step"] * 1e-3,
+                                                   min(steps, 3), 1)
     if name == "c1" and not args.no_dscreen:
         res["density_screening"] = bench_dscreen(args, torch, plan, wl, res["fp64"]["ms_per_step"] * 1e-3, steps,
                                                  warmup)
@@ -343,6 +346,25 @@ def bench_batch(args, torch, jk, synth, steps, warmup):
     for p in plans:
         p.close()
     return res
+
+
+def bench_deterministic(torch, jk, plan, D, g, wl, dt_full, steps, warmup):
+    """The fixed-order FP64 build (JK_DETERMINISTIC): its time against the
+    default build, whether two builds agree bit for bit, and its error
+    against the oracle's stored values."""
+    import numpy as np
+    flags = jk.JK_DO_J | jk.JK_DO_K | jk.JK_DETERMINISTIC
+    J = torch.empty_like(D)
+    K = torch.empty_like(D)
+    dt = timed_loop(lambda: plan.execute(D, J, K, flags=flags), steps, warmup, torch)
+    J1, K1 = J.cpu().numpy(), K.cpu().numpy()
+    plan.execute(D, J, K, flags=flags)
+    torch.cuda.synchronize()
+    same = bool(np.array_equal(J1, J.cpu().numpy()) and np.array_equal(K1, K.cpu().numpy()))
+    err = errors_vs_golden(g, wl.D, J, K)
+    log(f"deterministic fp64: {dt * 1e3:.2f} ms/build ({dt / dt_full:.2f} x the default build), "
+        f"bitwise repeatable {same}" + (f", max|dJ| {err['max_dJ']:.1e} max|dK| {err['max_dK']:.1e}" if err else ""))
+    return {"ms_per_step": dt * 1e3, "vs_default_build": dt / dt_full, "bitwise_repeatable": same, "vs_oracle": err}
 
 
 def bench_dscreen(args, torch, plan, wl, dt_full, steps, warmup):
