@@ -279,7 +279,7 @@ def bench_molecule(name, args, torch, jk, synth, steps, warmup):
         res[prec] = r
     if "fp64" in res and "mixed" in res:
         res["mixed"]["speedup_vs_fp64"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
-    if name in ("c1", "c2") and "fp64" in res:
+    if name in ("c1", "c2") and "fp64" in res and not args.no_deterministic:
         res["deterministic"] = bench_deterministic(torch, jk, plan, D, g, wl, res["fp64"]["ms_per_step"] * 1e-3,
                                                    min(steps, 3), 1)
     if name == "c1" and not args.no_dscreen:
@@ -499,6 +499,7 @@ def main():
     ap.add_argument("--precisions", default="fp64,mixed",
                     help="builds timed per molecule (fp64 is needed for the headline value)")
     ap.add_argument("--no-dscreen", action="store_true", help="skip the incremental (density-screened) build")
+    ap.add_argument("--no-deterministic", action="store_true", help="skip the fixed-order (JK_DETERMINISTIC) builds")
     ap.add_argument("--micro", action="store_true", help="only the appendix-B style micro-benchmarks")
     ap.add_argument("--dscreen", type=float, default=1e-10, help="density screening threshold")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
