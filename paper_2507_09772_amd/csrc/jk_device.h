@@ -971,6 +971,16 @@ struct BatchDesc {
     int32_t pad[3];
 };
 
+// The argument block of descriptor m.  The descriptors are written before
+// the launch and only read by the kernels, so they are read through the
+// constant address space: the compiler may then load a field where it is
+// used (and load it again later) instead of holding the whole block in
+// registers, which made the batched family-1 row kernels spill.
+__device__ __forceinline__ const JkArgs &desc_args(const BatchDesc *descs, int m) {
+    using CDesc = const __attribute__((address_space(4))) BatchDesc;
+    return *(const JkArgs *)&((CDesc *)descs)[m].a;
+}
+
 __device__ __forceinline__ int batch_desc(const BatchDesc *__restrict__ d, int n, int g) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -1200,8 +1210,7 @@ __global__ void __launch_bounds__(NT) jk_k1_row(const JkArgs a, const BatchDesc 
     if constexpr (BATCH) {
         const int g = blockIdx.x;
         const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
-        const JkArgs d = descs[m].a;
-        k1_row_task<LI, LJ, LK, LL, R, NT>(d, g - descs[m].tile_base);
+        k1_row_task<LI, LJ, LK, LL, R, NT>(desc_args(descs, m), g - descs[m].tile_base);
     } else {
         k1_row_task<LI, LJ, LK, LL, R, NT>(a, blockIdx.x);
     }
@@ -2035,8 +2044,7 @@ __global__ void __launch_bounds__(256) jk_k1_batch(const BatchDesc *__restrict__
     const int g = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (g >= total) return;
     const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
-    const JkArgs a = descs[m].a;
-    k1_tile<LI, LJ, LK, LL, R>(a, g - descs[m].tile_base);
+    k1_tile<LI, LJ, LK, LL, R>(desc_args(descs, m), g - descs[m].tile_base);
 }
 
 template <int LI, int LJ, int LK, int LL, typename R>
@@ -2052,7 +2060,7 @@ __global__ void __launch_bounds__(64) jk_k2_batch(const BatchDesc *__restrict__ 
     const int qq = lane_used ? q : 0;
     const int g = blockIdx.x;
     const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
-    const JkArgs a = descs[m].a;
+    const JkArgs &a = desc_args(descs, m);
     JK_K2_TILE(a, g - descs[m].tile_base);
 }
 
