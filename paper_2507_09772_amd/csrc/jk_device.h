@@ -1629,13 +1629,12 @@ __global__ void __launch_bounds__(NT) jk_k2_row(const JkArgs a_in, const BatchDe
     constexpr int QW = F::QW, LPQ = F::LPQ, NW = NT / 64;
     extern __shared__ double smem2[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_index();
-    int task = blockIdx.x;
-    JkArgs a = a_in;
+    int task = blockIdx.x, m = 0;
     if constexpr (BATCH) {
-        const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, task));
-        a = descs[m].a;
+        m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, task));
         task -= descs[m].tile_base;
     }
+    const JkArgs &a = BATCH ? desc_args(descs, m) : a_in;
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
     const int segL = a.seg_same ? 0 : a.ncolK;
     const int per_set = (NI + NJ) * ncols + NAB;
@@ -1812,13 +1811,12 @@ __global__ void __launch_bounds__(NT) jk_k3_row(const JkArgs a_in, const BatchDe
     constexpr int LPQ = F::LPQ, QW = F::QW, NW = NT / 64, NCC = F::NCC, TS = F::TS, PB = F::PB;
     extern __shared__ double smem3[];
     const int tid = threadIdx.x, wave = tid >> 6, lane = lane_index();
-    int task = blockIdx.x;
-    JkArgs a = a_in;
+    int task = blockIdx.x, m = 0;
     if constexpr (BATCH) {
-        const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, task));
-        a = descs[m].a;
+        m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, task));
         task -= descs[m].tile_base;
     }
+    const JkArgs &a = BATCH ? desc_args(descs, m) : a_in;
     const int ncols = a.ncolK + (a.seg_same ? 0 : a.ncolL);
     const int segL = a.seg_same ? 0 : a.ncolK;
     const int per_set = (NI + NJ) * ncols + NAB;
