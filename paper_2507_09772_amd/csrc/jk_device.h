@@ -738,11 +738,14 @@ __device__ __forceinline__ void k1_compute_op(const JkArgs &a, const PairRec &B,
         using P = RootPipe<NR, R>;
         // the next ket primitive's record loads while the current one's bra
         // primitives run
+        // (the one-root classes load each ket record when they reach it:
+        // their registers, not the load, bound them)
+        constexpr bool PREF = NR > 1;
         PrimPair pk = a.pp[Kt.pp_off];
         settle(pk);
         for (int ik = 0; ik < npk; ++ik) {
             PrimPair pkn;
-            if (ik + 1 < npk) pkn = a.pp[Kt.pp_off + (ik + 1) * Kt.pp_stride];
+            if (PREF && ik + 1 < npk) pkn = a.pp[Kt.pp_off + (ik + 1) * Kt.pp_stride];
             PT<R> t = prim_T<R>(pbat(0), pk);
             typename P::Row row;
             P::fetch(t.T, a.tab, row);
@@ -757,8 +760,12 @@ __device__ __forceinline__ void k1_compute_op(const JkArgs &a, const PairRec &B,
                 k1_roots_acc<LI, LJ, LK, LL, R>(g, u, w, ab, cd, V);
             }
             if (ik + 1 < npk) {
-                settle(pkn);
-                pk = pkn;
+                if constexpr (PREF) {
+                    settle(pkn);
+                    pk = pkn;
+                } else {
+                    pk = a.pp[Kt.pp_off + (ik + 1) * Kt.pp_stride];
+                }
             }
         }
         return;
