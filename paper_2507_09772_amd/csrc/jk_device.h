@@ -1212,8 +1212,15 @@ __device__ __forceinline__ void k1_row_task(const JkArgs &a, int task) {
     }
 }
 
+// Waves per SIMD the compiler is held to for a family-1 row kernel: five
+// for the FP64 (ps|ss) class (96 VGPRs; left to itself it takes 101, four
+// waves), none otherwise.
+constexpr int k1_row_waves(int li, int lj, int lk, int ll, int rsize) {
+    return (li + lj + lk + ll == 1 && rsize == 8) ? 5 : 1;
+}
 template <int LI, int LJ, int LK, int LL, typename R, int NT, bool BATCH>
-__global__ void __launch_bounds__(NT) jk_k1_row(const JkArgs a, const BatchDesc *__restrict__ descs, int ndesc) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(k1_row_waves(LI, LJ, LK, LL, sizeof(R)))))
+jk_k1_row(const JkArgs a, const BatchDesc *__restrict__ descs, int ndesc) {
     if constexpr (BATCH) {
         const int g = blockIdx.x;
         const int m = __builtin_amdgcn_readfirstlane(batch_desc(descs, ndesc, g));
